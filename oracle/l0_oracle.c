@@ -1,0 +1,252 @@
+/*
+ * ORACLE — TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded FP64 implementation of Serial-l0 and
+ * Parallel-l0 (Mendoza-Smith & Tanner, "Expander l0-decoding", Algorithms 1
+ * and 2, selection rule eq. (selection_l0) in Section 3).  Only the test
+ * suite, the package's smoke check and the benchmark's CPU-baseline leg call
+ * it; the GPU decoder shares no code with it.  Built with -O2
+ * -ffp-contract=off and no fast-math, so every sum, difference and
+ * comparison below is one IEEE-754 binary64 operation in the order written.
+ *
+ * Readings of the paper that this file fixes (the paper leaves them open):
+ *  - zero test and equality: with tau = tol * max_i |y_i|, an entry v counts
+ *    as nonzero iff |v| > tau; the paper's exact equality is tol = 0;
+ *  - candidate values: for column j only the nonzero values of r on N(j) are
+ *    tried as omega (any other omega leaves every entry of r_N(j) nonzero
+ *    when tau = 0, so it cannot decrease ||r||_0);
+ *  - one update per column: among the candidates reaching the largest
+ *    decrease, the smallest value is taken (Algorithms 1-2 write "for omega
+ *    in T"; adding two different values to one entry is not a correction);
+ *  - threshold: decreases are integers, so "decrease >= alpha" is
+ *    "decrease >= ceil(alpha)";
+ *  - r <- y - A x_hat is recomputed from scratch (Algorithm 2, last step):
+ *    s_i = sum over ascending columns j with i in N(j) of x_hat_j, starting
+ *    from +0.0, then r_i = y_i - s_i;
+ *  - "while not converged" stops on ||r||_0 = 0 (CONVERGED), on an empty
+ *    update set (STALLED: r no longer changes) or after max_iter residual
+ *    updates (MAX_ITER); an iteration is the work between two residual
+ *    updates (Definition 3.1).
+ * Rule MODE scores a candidate by its frequency in r_N(j) instead of the
+ * l0-decrease (parallel-LDDSR, Section 4.3 and Table 2).
+ */
+#include <limits.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ORC_RULE_L0DEC = 0, ORC_RULE_MODE = 1 };
+enum { ORC_CONVERGED = 0, ORC_STALLED = 1, ORC_MAX_ITER = 2 };
+
+static int is_nonzero(double v, double tau) { return fabs(v) > tau; }
+
+/*
+ * Score of one column on residual values v[0..d) = r restricted to N(j)
+ * (eq. (selection_l0)).  For every nonzero candidate omega = v[t] the
+ * l0-decrease is ||r||_0 - ||r - omega a_j||_0; only the d rows of N(j)
+ * change, so it is counted on them.  Returns 1 and sets *omega when the best
+ * decrease reaches a; *best gets the best score (INT_MIN if no candidate).
+ */
+static int score_column(int32_t d, const double* v, double tau, int32_t rule, int32_t a,
+                        double* omega, int32_t* best) {
+    int32_t before = 0;
+    for (int32_t u = 0; u < d; ++u) before += is_nonzero(v[u], tau);
+    int32_t top = INT_MIN;
+    double w = 0.0;
+    for (int32_t t = 0; t < d; ++t) {
+        if (!is_nonzero(v[t], tau)) continue;
+        int32_t after = 0, freq = 0;
+        for (int32_t u = 0; u < d; ++u) {
+            double diff = v[u] - v[t];
+            after += is_nonzero(diff, tau);
+            freq += !is_nonzero(diff, tau);
+        }
+        int32_t score = (rule == ORC_RULE_MODE) ? freq : before - after;
+        if (top == INT_MIN || score > top || (score == top && v[t] < w)) {
+            top = score;
+            w = v[t];
+        }
+    }
+    *best = top;
+    *omega = w;
+    return top != INT_MIN && top >= a;
+}
+
+static int args_ok(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const double* y,
+                   double alpha, int32_t rule, int32_t max_iter, double tol) {
+    if (n < 1 || m < 1 || d < 2 || d > m || !col_idx || !y) return 0;
+    if (!(alpha > 1.0) || !(alpha <= (double)d)) return 0;
+    if (rule != ORC_RULE_L0DEC && rule != ORC_RULE_MODE) return 0;
+    if (max_iter < 0 || !(tol >= 0.0) || !isfinite(tol)) return 0;
+    for (int64_t e = 0; e < n * (int64_t)d; ++e)
+        if (col_idx[e] < 0 || col_idx[e] >= m) return 0;
+    for (int32_t i = 0; i < m; ++i)
+        if (!isfinite(y[i])) return 0;
+    return 1;
+}
+
+static double zero_threshold(int32_t m, const double* y, double tol) {
+    double s = 0.0;
+    for (int32_t i = 0; i < m; ++i)
+        if (fabs(y[i]) > s) s = fabs(y[i]);
+    return tol * s;
+}
+
+/* r = y - A x, each (A x)_i summed from +0.0 over ascending columns. */
+void orc_residual(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const double* y,
+                  const double* x, double* r) {
+    double* s = (double*)calloc((size_t)m, sizeof(double));
+    for (int64_t j = 0; j < n; ++j)
+        for (int32_t t = 0; t < d; ++t) s[col_idx[j * d + t]] += x[j];
+    for (int32_t i = 0; i < m; ++i) r[i] = y[i] - s[i];
+    free(s);
+}
+
+static int32_t count_nonzero(int32_t m, const double* r, double tau) {
+    int32_t c = 0;
+    for (int32_t i = 0; i < m; ++i) c += is_nonzero(r[i], tau);
+    return c;
+}
+
+/*
+ * Score every column in cols[0..ncols) on the given residual (absolute
+ * threshold tau).  sel[c] = 1 and omega[c] = the update when selected;
+ * best[c] = best score.  Used to check a single vote step in isolation.
+ */
+void orc_score_columns(int64_t ncols, int32_t d, const int32_t* rows, const double* r, double tau,
+                       int32_t rule, int32_t a, uint8_t* sel, double* omega, int32_t* best) {
+    double* v = (double*)malloc(sizeof(double) * (size_t)d);
+    for (int64_t c = 0; c < ncols; ++c) {
+        for (int32_t t = 0; t < d; ++t) v[t] = r[rows[c * d + t]];
+        sel[c] = (uint8_t)score_column(d, v, tau, rule, a, &omega[c], &best[c]);
+        if (!sel[c]) omega[c] = 0.0;
+    }
+    free(v);
+}
+
+/*
+ * ||r||_0 - ||r - omega a_j||_0 over the whole m-vector, forming r - omega a_j
+ * entry by entry (the definition in eq. (selection_l0), used as a pin).
+ */
+int32_t orc_literal_decrease(int32_t m, int32_t d, const int32_t* rows, const double* r,
+                             double omega, double tau) {
+    double* q = (double*)malloc(sizeof(double) * (size_t)m);
+    memcpy(q, r, sizeof(double) * (size_t)m);
+    for (int32_t t = 0; t < d; ++t) q[rows[t]] = r[rows[t]] - omega;
+    int32_t dec = count_nonzero(m, r, tau) - count_nonzero(m, q, tau);
+    free(q);
+    return dec;
+}
+
+/*
+ * Parallel-l0 (Algorithm 2).  x_init (optional) resumes from a previous
+ * estimate; x_out[n] receives x_hat.  trace[0..iters] receives ||r||_0 after
+ * each residual update (trace[0] for the start), tsize[0..iters) the number
+ * of columns updated in each iteration; both need max_iter+1 / max_iter
+ * slots.  Returns 0, or -1 on invalid arguments.
+ */
+int orc_parallel_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const double* y,
+                    double alpha, int32_t rule, int32_t max_iter, double tol, const double* x_init,
+                    double* x_out, int32_t* trace, int64_t* tsize, int32_t* iters,
+                    int32_t* outcome) {
+    if (!args_ok(n, m, d, col_idx, y, alpha, rule, max_iter, tol) || !x_out || !trace || !iters ||
+        !outcome)
+        return -1;
+    const int32_t a = (int32_t)ceil(alpha);
+    const double tau = zero_threshold(m, y, tol);
+    double* r = (double*)malloc(sizeof(double) * (size_t)m);
+    double* v = (double*)malloc(sizeof(double) * (size_t)d);
+    double* omega = (double*)malloc(sizeof(double) * (size_t)n);
+    uint8_t* sel = (uint8_t*)malloc((size_t)n);
+
+    for (int64_t j = 0; j < n; ++j) x_out[j] = x_init ? x_init[j] : 0.0;
+    orc_residual(n, m, d, col_idx, y, x_out, r);
+    int32_t l = 0;
+    trace[0] = count_nonzero(m, r, tau);
+    for (;;) {
+        if (trace[l] == 0) { *outcome = ORC_CONVERGED; break; }
+        if (l == max_iter) { *outcome = ORC_MAX_ITER; break; }
+        /* every column is scored on the same residual */
+        int64_t chosen = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            int32_t best;
+            for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d + t]];
+            sel[j] = (uint8_t)score_column(d, v, tau, rule, a, &omega[j], &best);
+            chosen += sel[j];
+        }
+        if (chosen == 0) { *outcome = ORC_STALLED; break; }
+        for (int64_t j = 0; j < n; ++j)
+            if (sel[j]) x_out[j] = x_out[j] + omega[j];
+        orc_residual(n, m, d, col_idx, y, x_out, r);
+        if (tsize) tsize[l] = chosen;
+        ++l;
+        trace[l] = count_nonzero(m, r, tau);
+    }
+    *iters = l;
+    free(r); free(v); free(omega); free(sel);
+    return 0;
+}
+
+/*
+ * Serial-l0 (Algorithm 1): columns are visited in ascending order, each scored
+ * on the current residual; a selected column takes its single best update and
+ * the d residual entries on N(j) are recomputed at once (each from +0.0 over
+ * the ascending columns of its row).  A sweep is one pass over all n
+ * columns.  *updates counts residual updates (the paper's iterations),
+ * *sweeps the passes; the run stops when ||r||_0 = 0 at the start of a sweep
+ * (CONVERGED), after a sweep without updates (STALLED) or after max_sweeps
+ * sweeps (MAX_ITER).  Returns 0, or -1 on invalid arguments.
+ */
+int orc_serial_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const double* y,
+                  double alpha, int32_t rule, int32_t max_sweeps, double tol, double* x_out,
+                  int64_t* updates, int32_t* sweeps, int32_t* outcome, int32_t* final_nnz) {
+    if (!args_ok(n, m, d, col_idx, y, alpha, rule, max_sweeps, tol) || !x_out || !updates ||
+        !sweeps || !outcome)
+        return -1;
+    const int32_t a = (int32_t)ceil(alpha);
+    const double tau = zero_threshold(m, y, tol);
+    /* rows of A as ascending column lists (a counting sort over columns) */
+    int64_t* rowptr = (int64_t*)calloc((size_t)m + 1, sizeof(int64_t));
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)m);
+    int64_t* rowcol = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n * d));
+    for (int64_t e = 0; e < n * (int64_t)d; ++e) rowptr[col_idx[e] + 1]++;
+    for (int32_t i = 0; i < m; ++i) rowptr[i + 1] += rowptr[i];
+    for (int32_t i = 0; i < m; ++i) fill[i] = rowptr[i];
+    for (int64_t j = 0; j < n; ++j)
+        for (int32_t t = 0; t < d; ++t) rowcol[fill[col_idx[j * d + t]]++] = j;
+
+    double* r = (double*)malloc(sizeof(double) * (size_t)m);
+    double* v = (double*)malloc(sizeof(double) * (size_t)d);
+    for (int64_t j = 0; j < n; ++j) x_out[j] = 0.0;
+    for (int32_t i = 0; i < m; ++i) r[i] = y[i];
+    int64_t upd = 0;
+    int32_t sw = 0;
+    for (;;) {
+        if (count_nonzero(m, r, tau) == 0) { *outcome = ORC_CONVERGED; break; }
+        if (sw == max_sweeps) { *outcome = ORC_MAX_ITER; break; }
+        int any = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            double w;
+            int32_t best;
+            for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d + t]];
+            if (!score_column(d, v, tau, rule, a, &w, &best)) continue;
+            x_out[j] = x_out[j] + w;
+            ++upd;
+            any = 1;
+            for (int32_t t = 0; t < d; ++t) {
+                int32_t i = col_idx[j * d + t];
+                double s = 0.0;
+                for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) s += x_out[rowcol[p]];
+                r[i] = y[i] - s;
+            }
+        }
+        ++sw;
+        if (!any) { *outcome = ORC_STALLED; break; }
+    }
+    *updates = upd;
+    *sweeps = sw;
+    if (final_nnz) *final_nnz = count_nonzero(m, r, tau);
+    free(rowptr); free(fill); free(rowcol); free(r); free(v);
+    return 0;
+}

@@ -1,0 +1,77 @@
+"""The oracle's pins must catch plausible mistakes.  Each mutant below is a
+copy of the oracle source with one planted error (a sign, an index, a
+threshold, a tie-break, a dropped term); it is compiled into a temporary
+library and the pin checks are re-run against it: every mutant must fail at
+least one of them.  Mistakes are planted in the oracle on the CPU only."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import test_oracle as pins
+from golden_io import decode_cases
+
+MUTANTS = {
+    "residual_sign": ("r[i] = y[i] - s[i];", "r[i] = y[i] + s[i];"),
+    "update_sign": ("x_out[j] = x_out[j] + omega[j];", "x_out[j] = x_out[j] - omega[j];"),
+    "tie_break_largest": ("(score == top && v[t] < w)", "(score == top && v[t] > w)"),
+    "drop_zero_count": ("? freq : before - after;", "? freq : d - after;"),
+    "threshold_floor": ("const int32_t a = (int32_t)ceil(alpha);\n    const double tau = zero_threshold(m, y, tol);\n    double* r",
+                        "const int32_t a = (int32_t)floor(alpha);\n    const double tau = zero_threshold(m, y, tol);\n    double* r"),
+    "strict_threshold": ("return top != INT_MIN && top >= a;", "return top != INT_MIN && top > a;"),
+    "zero_test_nonstrict": ("return fabs(v) > tau;", "return fabs(v) >= tau;"),
+    "gather_index": ("for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d + t]];\n            sel[j]",
+                     "for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d]];\n            sel[j]"),
+    "residual_skips_last_row": ("for (int32_t i = 0; i < m; ++i) r[i] = y[i] - s[i];",
+                                "for (int32_t i = 0; i + 1 < m; ++i) r[i] = y[i] - s[i];"),
+    "serial_row_recompute_missing": ("r[i] = y[i] - s;", "r[i] = y[i] - s * (t == 0);"),
+    "tau_absolute": ("return tol * s;", "return tol;"),
+}
+
+
+def _run_pins():
+    """Run the pin checks; return the names of those that fail."""
+    failed = []
+    checks = [("scorer", pins.test_scorer_cases)]
+    for c in decode_cases():
+        checks.append((f"worked-{c[0]}-{c[4]['algo']}-{c[4]['rule']}-{c[4]['alpha']}",
+                       lambda c=c: pins.test_worked_decodes(c)))
+    checks += [
+        ("closed_form_count", lambda: [pins.test_score_equals_count_closed_form(t, r)
+                                       for t in (0.0, 1e-10) for r in (0, 1)]),
+        ("disjoint", pins.test_disjoint_columns_one_iteration),
+        ("k1", lambda: pins.test_k1_recovers_in_one_iteration(0)),
+        ("true_updates", lambda: pins.test_updates_are_true_values_and_trace_decreases(0)),
+        ("scaling", lambda: [pins.test_power_of_two_scaling_bitwise(e) for e in (-40, 5)]),
+        ("serial_parallel", pins.test_serial_and_parallel_agree),
+    ]
+    for name, fn in checks:
+        try:
+            fn()
+        except (AssertionError, ValueError):
+            failed.append(name)
+    return failed
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path, monkeypatch):
+    with open(oracle._SRC) as f:
+        src = f.read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    path = os.path.join(tmp_path, "mut.c")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    lib = os.path.join(tmp_path, "libmut.so")
+    subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-std=c11", "-o", lib, path,
+                    "-lm"], check=True)
+    monkeypatch.setattr(oracle, "_LIB", lib)
+    monkeypatch.setattr(oracle, "_lib", None)
+    failed = _run_pins()
+    assert failed, f"mutant {name} passed every pin"
+
+
+def test_unmutated_oracle_passes_all_pins():
+    assert _run_pins() == []
