@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark: Parallel-l0 decoding of the n = 2^24 instance on one MI355X.
+
+Workload: n = 2^24, m = 16777 (n/m ~ 10^3, residual held in LDS), d = 7,
+k = floor(0.25 m) = 4194, nonzeros iid N(0,1) in FP64, alpha = ceil(d/2) = 4,
+tol = 1e-10, max_iter = 100; A has d distinct uniform rows per column.
+Inputs are seeded and synthetic and are resident in HBM before timing.
+
+A step is one complete decode through the C-ABI (l0_decode_ex): repacking
+the column-index store, then the persistent solve kernel (every vote,
+residual update and ||r||_0 count until the loop stops).  `value` is decodes
+per second.  The roofline object is for the dominant kernel, the persistent
+solve kernel, timed with HIP events on the stream it runs on (torch's current
+stream) over repeated l0_solve calls on the prepared matrix; its algorithmic
+bytes per launch are the per-vote-pass bytes 4nd (streamed column-index
+store) times the number of vote passes, plus 16m per residual pass and the
+x_hat initialisation 8n.  The CPU baseline is the FP64 oracle (one thread)
+on one full decode of the same instance.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Parallel-ℓ0 solve time & HBM GB/s at n=2^24; batched solves/sec vs plain"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1508_01256_amd/csrc/l0_kernels.hip", "paper_1508_01256_amd/csrc/l0_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_kernel_n2^24_traffic.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per solve launch from the committed rocprofv3 counter runs,
+    or None when the kernel source changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def algorithmic_bytes(n, m, d, iters, outcome, tsizes):
+    """Bytes the method must move in one solve launch (see module doc)."""
+    passes = iters + (1 if outcome == 1 else 0)  # a stalled run votes once more, finding T empty
+    b = 8 * n                      # x_hat = 0
+    b += 16 * m                    # r = y (read y, write r)
+    b += passes * 4 * n * d        # column-index stream per vote pass
+    b += iters * 16 * m            # residual pass: y read + r write (upper bound per row touched)
+    b += sum(int(t) for t in tsizes) * (16 + 4 * d)  # x_hat RMW + support-list appends
+    return b, passes
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--repeats", type=int, default=30, help="l0_solve launches timed for the roofline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--kind", choices=["normal", "pm1"], default="normal")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the decoder has no "
+              "multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1508_01256_amd as l0
+
+    torch.cuda.set_device(0)
+    kind = gen.VALUES_NORMAL if args.kind == "normal" else gen.VALUES_PM1
+    t0 = time.time()
+    inst = gen.single_workload("n2^24", 0, kind=kind)
+    n, m, d, alpha, max_iter, tol = inst.n, inst.m, inst.d, inst.alpha, 100, 1e-10
+    print(f"[bench] generated n={n} m={m} d={d} k={inst.k} in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    col = torch.from_numpy(inst.col_idx).cuda()
+    y = torch.from_numpy(inst.y).cuda()
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    res = l0.new_result()
+    ws = torch.empty(l0.l0_workspace_bytes(n, m, d, max_iter), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        st = l0.l0_decode_ex(col, n, m, d, y, alpha, max_iter, tol, x, None, res, ws)
+        if st != l0.L0_OK:
+            raise RuntimeError(f"l0_decode_ex status {st}")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    r = res.cpu()
+    iters, outcome = (int(v) for v in r[:1].view(torch.int32).tolist())
+    print(f"[bench] one-shot decode {ms_per_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f}), "
+          f"iters={iters} outcome={l0.OUTCOME_NAMES[outcome]}", file=sys.stderr, flush=True)
+
+    # dominant kernel: the persistent solve kernel on a prepared matrix
+    A = l0.Matrix(col, n, m, d)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    A2 = l0.Matrix(col, n, m, d)
+    torch.cuda.synchronize()
+    prep_ms = (time.perf_counter() - p0) * 1e3
+    A2.close()
+    trace = torch.full((max_iter + 1,), -1, dtype=torch.int32, device="cuda")
+    tsize = torch.zeros(max_iter, dtype=torch.int64, device="cuda")
+    xs, rs = A.solve_async(y, alpha, max_iter=max_iter, tol=tol, trace=trace, tsize=tsize)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.repeats)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.repeats)]
+    for i in range(args.repeats):
+        starts[i].record(stream)
+        A.solve_async(y, alpha, max_iter=max_iter, tol=tol, x=xs, res=rs, trace=trace, tsize=tsize)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    solve_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    solve_avg = float(np.mean(solve_ms))
+    rr = rs.cpu()
+    s_iters, s_outcome = (int(v) for v in rr[:1].view(torch.int32).tolist())
+    assert (s_iters, s_outcome) == (iters, outcome)
+    assert torch.equal(xs, x), "prepared-matrix solve differs from the one-shot decode"
+    ts = tsize[:iters].cpu().tolist()
+    tr = trace[: iters + 1].cpu().tolist()
+    bytes_launch, passes = algorithmic_bytes(n, m, d, iters, outcome, ts)
+    achieved = bytes_launch / (solve_avg * 1e-3) / 1e9
+    vote_bytes = 4 * n * d
+    print(f"[bench] solve kernel avg {solve_avg:.3f} ms (min {min(solve_ms):.3f}) over {args.repeats}; "
+          f"passes={passes} trace={tr} tsize={ts}; {achieved:.0f} GB/s algorithmic; "
+          f"prep {prep_ms:.2f} ms", file=sys.stderr, flush=True)
+    A.close()
+
+    traffic = measured_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "l0::solve_kernel<7,true>", "bytes_per_launch": bytes_launch,
+                "avg_launch_ms": round(solve_avg, 4)}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        c0 = time.perf_counter()
+        o = oracle.parallel_l0(n, m, d, inst.col_idx, inst.y, alpha, max_iter=max_iter, tol=tol)
+        cdt = time.perf_counter() - c0
+        ok = (o["iters"] == iters and np.array_equal(o["x"], xs.cpu().numpy()))
+        cpu = {"value": round(1.0 / cdt, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"1 full decode of the same n=2^24 instance ({cdt:.1f} s, single thread, "
+                         f"gcc -O2; parity with GPU: {'bitwise' if ok else 'MISMATCH'})"}
+        print(f"[bench] oracle {cdt:.2f} s/solve, parity {'ok' if ok else 'MISMATCH'}",
+              file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": round(1e3 / ms_per_step, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"Parallel-l0 single instance n=2^24 m={m} d={d} k={inst.k} "
+                               f"alpha={alpha:g} tol={tol:g} max_iter={max_iter} "
+                               f"{'N(0,1)' if kind == 0 else 'uniform +-1'} nonzeros, seed {inst.seed}",
+                   "n": n, "m": m, "d": d, "k": inst.k, "alpha": alpha, "step": "l0_decode_ex (repack + solve)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": {"iters": iters, "outcome": l0.OUTCOME_NAMES[outcome], "trace": tr, "tsize": ts,
+                   "vote_passes": passes, "solve_prepared_ms": round(solve_avg, 4),
+                   "solve_prepared_min_ms": round(min(solve_ms), 4),
+                   "per_vote_pass_us": round(solve_avg * 1e3 / max(passes, 1), 2),
+                   "vote_bytes_per_pass": vote_bytes, "prepare_ms": round(prep_ms, 3),
+                   "solves_per_s_prepared": round(1e3 / solve_avg, 3)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -127,14 +127,19 @@ class Instance:
         return x
 
 
+def default_alpha(d: int) -> float:
+    """ceil(d/2), raised to 2 for d = 2 (alpha must lie in (1, d])."""
+    return float(max(math.ceil(d / 2), 2))
+
+
 def make_instance(seed: int, n: int, m: int, d: int, k: int, *, alpha: float | None = None,
                   kind: int = VALUES_NORMAL) -> Instance:
-    """Draw A, a k-sparse x and y = A x; alpha defaults to ceil(d/2)."""
+    """Draw A, a k-sparse x and y = A x; alpha defaults to default_alpha(d)."""
     col = columns(seed, n, m, d)
     supp = support(seed, n, k)
     vals = values(seed, supp, kind)
     y = measure(n, m, d, col, supp, vals)
-    a = float(math.ceil(d / 2)) if alpha is None else float(alpha)
+    a = default_alpha(d) if alpha is None else float(alpha)
     return Instance(n, m, d, k, seed, col, supp, vals, y, a, kind)
 
 

@@ -1,0 +1,184 @@
+/*
+ * l0decode — Parallel-l0 expander decoding on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Mendoza-Smith & Tanner, "Expander l0-decoding", Algorithm 2 and
+ * its Data/Result lines): given the adjacency matrix A of a left d-regular
+ * bipartite expander (Definition 2.2: A is m x n, binary, exactly d ones per
+ * column), a measurement y = A x of a k-sparse x, and a threshold
+ * alpha in (1, d], find x_hat with y = A x_hat by repeating
+ *     T <- {(j, omega) : ||r||_0 - ||r - omega a_j||_0 >= alpha}
+ *     x_hat_j <- x_hat_j + omega for (j, omega) in T
+ *     r <- y - A x_hat
+ * where every column j is scored on the same residual r (eq. (selection_l0),
+ * Section 3).
+ *
+ * Conventions shared by every entry point:
+ *  - A is passed as col_idx: int32[n*d], column j's d row indices at
+ *    col_idx[j*d .. j*d+d), each in [0, m).  Row order inside a column does
+ *    not matter.
+ *  - Zero test and equality use tau = tol * max_i |y_i| (or tau = tol with
+ *    L0_TOL_ABSOLUTE): an entry v is nonzero iff |v| > tau, and two values
+ *    a, b are equal iff |a - b| <= tau (tol = 0 is exact equality).
+ *  - The candidates for omega are the nonzero residual values on N(j); the
+ *    decrease is an integer, so it is compared with ceil(alpha); a column
+ *    takes one update, the smallest candidate among those with the largest
+ *    decrease.
+ *  - r <- y - A x_hat recomputes each changed r_i as y_i minus the sum of
+ *    x_hat_j over the columns j with i in N(j), summed from +0.0 in ascending
+ *    j.  Results are deterministic: the same inputs give bitwise the same
+ *    x_hat, iteration count and ||r||_0 trace on every run.
+ *  - Iterations (Definition 3.1) count residual updates.  The loop ends when
+ *    ||r||_0 = 0 (L0_CONVERGED), when no column qualifies (L0_STALLED; r would
+ *    never change again) or after max_iter iterations (L0_MAX_ITER).
+ *    Non-convergence is an outcome, not an error.
+ *  - All pointers documented as "device" are device memory (hipMalloc or
+ *    torch CUDA tensors) owned by the caller unless stated otherwise.  Every
+ *    call is asynchronous and ordered on `stream`; outputs are valid after the
+ *    stream synchronises.  Argument errors are detected on the host before
+ *    any device work and returned as L0_ERR_ARG; problems found by the device
+ *    (bad row index, non-finite y) are reported through the outcome.
+ */
+#ifndef L0DECODE_H
+#define L0DECODE_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Returned synchronously by every call. */
+typedef enum {
+    L0_OK = 0,
+    L0_ERR_ARG = 1,      /* invalid argument; nothing was enqueued */
+    L0_ERR_OOM = 2,      /* device allocation failed */
+    L0_ERR_HIP = 3,      /* a HIP runtime call failed */
+    L0_ERR_WORKSPACE = 4 /* caller workspace smaller than required */
+} l0_status;
+
+/* Written on the device into l0_result.outcome. */
+typedef enum {
+    L0_CONVERGED = 0,
+    L0_STALLED = 1,
+    L0_MAX_ITER = 2,
+    L0_DEV_BAD_INDEX = 16,   /* a row index outside [0, m) (when checked) */
+    L0_DEV_NONFINITE_Y = 17, /* y holds NaN or Inf */
+    L0_DEV_ABORTED = 19      /* the device loop timed out waiting for itself */
+} l0_outcome;
+
+typedef enum {
+    L0_RULE_L0DEC = 0, /* score = l0-decrease ||r||_0 - ||r - omega a_j||_0 (Algorithm 2) */
+    L0_RULE_MODE = 1   /* score = frequency of omega in r_N(j) (parallel-LDDSR, Table 2) */
+} l0_rule;
+
+typedef enum {
+    L0_TOL_RELATIVE = 0, /* tau = tol * max_i |y_i| */
+    L0_TOL_ABSOLUTE = 1  /* tau = tol */
+} l0_tol_mode;
+
+/* Per-solve summary, written on the device. */
+typedef struct {
+    int32_t iters;        /* residual updates performed */
+    int32_t outcome;      /* l0_outcome */
+    int32_t final_nnz;    /* ||r||_0 when the loop ended */
+    int32_t support_size; /* columns of x_hat ever updated */
+    int64_t updates;      /* total (j, omega) pairs applied over all iterations */
+} l0_result;
+
+/* Optional behaviour of l0_decode_ex / l0_solve; NULL means all defaults. */
+typedef struct {
+    int32_t rule;          /* l0_rule, default L0_RULE_L0DEC */
+    int32_t tol_mode;      /* l0_tol_mode, default L0_TOL_RELATIVE */
+    int32_t reserved0;     /* must be 0 */
+    int32_t reserved1;     /* must be 0 */
+    const double* x_init;  /* device double[n] to resume from, or NULL for x_hat = 0 */
+    int32_t* trace;        /* device int32[max_iter+1]: ||r||_0 before iteration 1 and after
+                              each iteration (entries past iters are left as they were);
+                              or NULL */
+    int64_t* tsize;        /* device int64[max_iter]: |T| of each iteration, or NULL */
+} l0_opts;
+
+/* Library version string. */
+const char* l0_version(void);
+
+/* Human-readable name of a status or outcome code. */
+const char* l0_status_string(int32_t code);
+
+/*
+ * One-shot Parallel-l0 decode (Algorithm 2).
+ *   col_idx  device int32[n*d]      column-index store of A (read only)
+ *   n, m, d  sizes; 1 <= n, 2 <= d <= min(m, 20), n*d < 2^31
+ *   y        device double[m]       measurement (read only)
+ *   alpha    threshold in (1, d]
+ *   max_iter >= 0 iterations at most
+ *   tol      >= 0, finite; relative zero/equality threshold (see above)
+ *   x_out    device double[n]       receives x_hat (zeroed by the call)
+ *   iters_out device int32[1]       iterations on CONVERGED/STALLED/MAX_ITER;
+ *                                   minus the outcome code on a device error
+ * The library allocates and frees its workspace on `stream`
+ * (hipMallocAsync/hipFreeAsync).  Every row index is range-checked on the
+ * device before use; an index outside [0, m) ends the solve with
+ * L0_DEV_BAD_INDEX and leaves x_out zero.
+ */
+l0_status l0_decode(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y,
+                    double alpha, int32_t max_iter, double tol, double* x_out,
+                    int32_t* iters_out, hipStream_t stream);
+
+/*
+ * Bytes of device workspace l0_decode_ex needs for one problem of this shape
+ * (0 for invalid sizes).
+ */
+size_t l0_workspace_bytes(int64_t n, int32_t m, int32_t d, int32_t max_iter);
+
+/*
+ * One-shot decode with options, a device result and caller workspace.
+ *   opts       host pointer or NULL
+ *   res_out    device l0_result[1]
+ *   workspace  device memory of at least l0_workspace_bytes(n, m, d, max_iter),
+ *              256-byte aligned; owned by the caller, reusable after the call
+ *              completes on `stream`; never allocated or freed here
+ * Other arguments as l0_decode.
+ */
+l0_status l0_decode_ex(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y,
+                       double alpha, int32_t max_iter, double tol, double* x_out,
+                       const l0_opts* opts, l0_result* res_out, void* workspace,
+                       size_t ws_bytes, hipStream_t stream);
+
+/*
+ * A prepared matrix: the column-index store repacked once for coalesced
+ * streaming plus per-row capacities, so that many solves on the same A skip
+ * the setup.  The handle owns its device memory (allocated here with
+ * hipMalloc on the current device) until l0_matrix_destroy.
+ */
+typedef struct l0_matrix_s* l0_matrix;
+
+/*
+ * Build a prepared matrix from col_idx (as l0_decode); the work is enqueued
+ * on `stream` and col_idx may be released once the stream has passed it.
+ * Row indices are range-checked; solves on a matrix with a bad index end with
+ * L0_DEV_BAD_INDEX.  *out receives the handle (host object).
+ */
+l0_status l0_matrix_create(const int32_t* col_idx, int64_t n, int32_t m, int32_t d,
+                           l0_matrix* out, hipStream_t stream);
+
+/* Release a prepared matrix (synchronises the device first); NULL is a no-op. */
+l0_status l0_matrix_destroy(l0_matrix A);
+
+/* Bytes of workspace l0_solve needs for a prepared matrix. */
+size_t l0_solve_workspace_bytes(l0_matrix A, int32_t max_iter);
+
+/*
+ * Decode y against a prepared matrix.  Arguments as l0_decode_ex, with the
+ * workspace sized by l0_solve_workspace_bytes.
+ */
+l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter, double tol,
+                   double* x_out, const l0_opts* opts, l0_result* res_out, void* workspace,
+                   size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* L0DECODE_H */

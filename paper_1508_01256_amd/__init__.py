@@ -1,0 +1,237 @@
+"""Python binding of the l0decode C-ABI (include/l0decode.h).
+
+Parallel-l0 expander decoding (Mendoza-Smith & Tanner, "Expander
+l0-decoding", Algorithm 2) runs entirely in the HIP library
+``libl0decode.so``; this module only marshals arguments.  PyTorch supplies
+device memory and the current stream.  The same names as the C entry points
+are exported (``l0_decode``, ``l0_decode_ex``, ``l0_solve`` ...), plus
+:func:`decode` and :class:`Matrix` as conveniences over them.
+
+Importing works without the library; the first call raises
+:class:`LibraryMissing` if ``libl0decode.so`` has not been built (there is no
+fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libl0decode.so")
+
+# status codes (returned)
+L0_OK, L0_ERR_ARG, L0_ERR_OOM, L0_ERR_HIP, L0_ERR_WORKSPACE = 0, 1, 2, 3, 4
+# outcomes (written on the device)
+L0_CONVERGED, L0_STALLED, L0_MAX_ITER = 0, 1, 2
+L0_DEV_BAD_INDEX, L0_DEV_NONFINITE_Y, L0_DEV_ABORTED = 16, 17, 19
+OUTCOME_NAMES = {0: "CONVERGED", 1: "STALLED", 2: "MAX_ITER", 16: "DEV_BAD_INDEX",
+                 17: "DEV_NONFINITE_Y", 19: "DEV_ABORTED"}
+# rules and tolerance modes
+L0_RULE_L0DEC, L0_RULE_MODE = 0, 1
+L0_TOL_RELATIVE, L0_TOL_ABSOLUTE = 0, 1
+
+#: every entry point declared in include/l0decode.h
+EXPORTED = ("l0_version", "l0_status_string", "l0_decode", "l0_workspace_bytes", "l0_decode_ex",
+            "l0_matrix_create", "l0_matrix_destroy", "l0_solve_workspace_bytes", "l0_solve")
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class L0Error(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what} failed with status {status}")
+        self.status = status
+
+
+class l0_opts(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("x_init", ctypes.c_void_p), ("trace", ctypes.c_void_p),
+                ("tsize", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libl0decode.so`` (ctypes), loading it on first use."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                                 "(or python -m paper_1508_01256_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, F64, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                ctypes.c_size_t)
+        L.l0_version.argtypes, L.l0_version.restype = [], ctypes.c_char_p
+        L.l0_status_string.argtypes, L.l0_status_string.restype = [I32], ctypes.c_char_p
+        L.l0_decode.argtypes = [P, I64, I32, I32, P, F64, I32, F64, P, P, P]
+        L.l0_workspace_bytes.argtypes, L.l0_workspace_bytes.restype = [I64, I32, I32, I32], SZ
+        L.l0_decode_ex.argtypes = [P, I64, I32, I32, P, F64, I32, F64, P, P, P, P, SZ, P]
+        L.l0_matrix_create.argtypes = [P, I64, I32, I32, ctypes.POINTER(P), P]
+        L.l0_matrix_destroy.argtypes = [P]
+        L.l0_solve_workspace_bytes.argtypes, L.l0_solve_workspace_bytes.restype = [P, I32], SZ
+        L.l0_solve.argtypes = [P, P, F64, I32, F64, P, P, P, P, SZ, P]
+        for f in ("l0_decode", "l0_decode_ex", "l0_matrix_create", "l0_matrix_destroy", "l0_solve"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(st, what):
+    if st != L0_OK:
+        raise L0Error(st, what)
+
+
+# ---------------------------------------------------------------------------
+# one-to-one wrappers of the C entry points (tensors in, status out)
+# ---------------------------------------------------------------------------
+
+def l0_version() -> str:
+    return lib().l0_version().decode()
+
+
+def l0_status_string(code: int) -> str:
+    return lib().l0_status_string(code).decode()
+
+
+def l0_decode(col_idx, n, m, d, y, alpha, max_iter, tol, x_out, iters_out) -> int:
+    return lib().l0_decode(_ptr(col_idx), n, m, d, _ptr(y), float(alpha), max_iter, float(tol),
+                           _ptr(x_out), _ptr(iters_out), _stream())
+
+
+def l0_workspace_bytes(n, m, d, max_iter) -> int:
+    return lib().l0_workspace_bytes(n, m, d, max_iter)
+
+
+def _opts(rule, tol_mode, x_init, trace, tsize):
+    return l0_opts(rule, tol_mode, 0, 0, None if x_init is None else x_init.data_ptr(),
+                   None if trace is None else trace.data_ptr(),
+                   None if tsize is None else tsize.data_ptr())
+
+
+def l0_decode_ex(col_idx, n, m, d, y, alpha, max_iter, tol, x_out, opts, res_out, workspace) -> int:
+    return lib().l0_decode_ex(_ptr(col_idx), n, m, d, _ptr(y), float(alpha), max_iter, float(tol),
+                              _ptr(x_out), None if opts is None else ctypes.byref(opts),
+                              _ptr(res_out), _ptr(workspace),
+                              0 if workspace is None else workspace.numel(), _stream())
+
+
+def l0_matrix_create(col_idx, n, m, d):
+    h = ctypes.c_void_p()
+    st = lib().l0_matrix_create(_ptr(col_idx), n, m, d, ctypes.byref(h), _stream())
+    return st, h
+
+
+def l0_matrix_destroy(h) -> int:
+    return lib().l0_matrix_destroy(h)
+
+
+def l0_solve_workspace_bytes(h, max_iter) -> int:
+    return lib().l0_solve_workspace_bytes(h, max_iter)
+
+
+def l0_solve(h, y, alpha, max_iter, tol, x_out, opts, res_out, workspace) -> int:
+    return lib().l0_solve(h, _ptr(y), float(alpha), max_iter, float(tol), _ptr(x_out),
+                          None if opts is None else ctypes.byref(opts), _ptr(res_out),
+                          _ptr(workspace), 0 if workspace is None else workspace.numel(), _stream())
+
+
+# ---------------------------------------------------------------------------
+# conveniences
+# ---------------------------------------------------------------------------
+
+def _result_dict(res, trace, tsize, x):
+    r = res.cpu()
+    iters, outcome, final_nnz, support = (int(v) for v in r[:3].view(torch.int32)[:4].tolist())
+    out = dict(x=x, iters=iters, outcome=outcome, final_nnz=final_nnz, support_size=support,
+               updates=int(r[2].item()))
+    if trace is not None and outcome < 16:
+        out["trace"] = trace[: iters + 1].cpu()
+    if tsize is not None and outcome < 16:
+        out["tsize"] = tsize[:iters].cpu()
+    return out
+
+
+def new_result(device="cuda"):
+    """A device buffer for one l0_result (24 bytes, as int64[3])."""
+    return torch.zeros(3, dtype=torch.int64, device=device)
+
+
+def decode(col_idx, y, n, m, d, alpha=None, *, max_iter=100, tol=1e-10, rule=L0_RULE_L0DEC,
+           tol_mode=L0_TOL_RELATIVE, x_init=None, want_trace=True):
+    """Decode y = A x on the GPU via l0_decode_ex; returns a dict with x (device
+    tensor), iters, outcome, final_nnz, support_size, updates, trace, tsize."""
+    dev = y.device
+    alpha = float(math.ceil(d / 2)) if alpha is None else float(alpha)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    trace = torch.full((max_iter + 1,), -1, dtype=torch.int32, device=dev) if want_trace else None
+    tsize = torch.zeros(max(max_iter, 1), dtype=torch.int64, device=dev) if want_trace else None
+    res = new_result(dev)
+    ws = torch.empty(l0_workspace_bytes(n, m, d, max_iter), dtype=torch.uint8, device=dev)
+    o = _opts(rule, tol_mode, x_init, trace, tsize)
+    _check(l0_decode_ex(col_idx, n, m, d, y, alpha, max_iter, tol, x, o, res, ws), "l0_decode_ex")
+    torch.cuda.current_stream().synchronize()
+    return _result_dict(res, trace, tsize, x)
+
+
+class Matrix:
+    """A prepared matrix (l0_matrix_create); solve() runs l0_solve on it."""
+
+    def __init__(self, col_idx, n, m, d):
+        st, h = l0_matrix_create(col_idx, n, m, d)
+        _check(st, "l0_matrix_create")
+        self.handle, self.n, self.m, self.d = h, n, m, d
+        self._ws = {}
+
+    def workspace(self, max_iter):
+        ws = self._ws.get(max_iter)
+        if ws is None:
+            nb = l0_solve_workspace_bytes(self.handle, max_iter)
+            ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            self._ws[max_iter] = ws
+        return ws
+
+    def solve_async(self, y, alpha, *, max_iter=100, tol=1e-10, rule=L0_RULE_L0DEC,
+                    tol_mode=L0_TOL_RELATIVE, x=None, res=None, trace=None, tsize=None,
+                    x_init=None, workspace=None):
+        """Enqueue one solve on the current stream; returns (x, res)."""
+        x = torch.empty(self.n, dtype=torch.float64, device=y.device) if x is None else x
+        res = new_result(y.device) if res is None else res
+        ws = self.workspace(max_iter) if workspace is None else workspace
+        o = _opts(rule, tol_mode, x_init, trace, tsize)
+        _check(l0_solve(self.handle, y, alpha, max_iter, tol, x, o, res, ws), "l0_solve")
+        return x, res
+
+    def solve(self, y, alpha, *, max_iter=100, tol=1e-10, rule=L0_RULE_L0DEC,
+              tol_mode=L0_TOL_RELATIVE, x_init=None, want_trace=True):
+        trace = torch.full((max_iter + 1,), -1, dtype=torch.int32, device=y.device) if want_trace else None
+        tsize = torch.zeros(max(max_iter, 1), dtype=torch.int64, device=y.device) if want_trace else None
+        x, res = self.solve_async(y, alpha, max_iter=max_iter, tol=tol, rule=rule, tol_mode=tol_mode,
+                                  trace=trace, tsize=tsize, x_init=x_init)
+        torch.cuda.current_stream().synchronize()
+        return _result_dict(res, trace, tsize, x)
+
+    def close(self):
+        if self.handle:
+            _check(l0_matrix_destroy(self.handle), "l0_matrix_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,301 @@
+// Host side of the l0decode C-ABI: argument checks, workspace layout and
+// kernel launches.  Every check happens before anything is enqueued.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "l0_internal.h"
+
+struct l0_matrix_s {
+    l0::MatrixView view;
+    void* base;
+    int device;
+};
+
+namespace l0 {
+
+MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d) {
+    MatrixBuffers b{};
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    b.soa = align256(static_cast<size_t>(ntiles) * d * kTile * sizeof(int32_t));
+    b.row_off = align256((static_cast<size_t>(m) + 1) * sizeof(int32_t));
+    b.deg = align256(static_cast<size_t>(m) * sizeof(int32_t));
+    b.flag = 256;
+    b.total = b.soa + b.row_off + b.deg + b.flag;
+    return b;
+}
+
+SolveBuffers solve_layout(int64_t n, int32_t m, int32_t d, int32_t max_iter) {
+    SolveBuffers b{};
+    b.ctrl = align256(sizeof(Ctrl));
+    b.counters = align256(2 * (static_cast<size_t>(max_iter) + 2) * sizeof(int32_t));
+    b.r = align256(static_cast<size_t>(m) * sizeof(double));
+    b.slot_cnt = b.slot_sorted = b.aff_flag = b.aff_list = align256(static_cast<size_t>(m) * sizeof(int32_t));
+    b.member = align256(static_cast<size_t>((n + 31) / 32) * sizeof(uint32_t));
+    b.slots = align256(static_cast<size_t>(n) * d * sizeof(int32_t));
+    b.total = b.ctrl + b.counters + b.r + 4 * b.slot_cnt + b.member + b.slots;
+    return b;
+}
+
+}  // namespace l0
+
+namespace {
+
+constexpr int32_t kMaxIterCap = 1 << 20;
+
+bool sizes_ok(int64_t n, int32_t m, int32_t d) {
+    if (n < 1 || m < 1 || d < l0::kDMin || d > l0::kDMax || d > m) return false;
+    if (n > INT32_MAX) return false;                  // column ids are stored as int32
+    if (n * static_cast<int64_t>(d) >= INT32_MAX) return false;  // row capacities are int32
+    return true;
+}
+
+bool solve_args_ok(double alpha, int32_t d, int32_t max_iter, double tol) {
+    if (!(alpha > 1.0) || !(alpha <= static_cast<double>(d))) return false;
+    if (max_iter < 0 || max_iter > kMaxIterCap) return false;
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return false;
+    return true;
+}
+
+bool opts_ok(const l0_opts* o) {
+    if (!o) return true;
+    if (o->rule != L0_RULE_L0DEC && o->rule != L0_RULE_MODE) return false;
+    if (o->tol_mode != L0_TOL_RELATIVE && o->tol_mode != L0_TOL_ABSOLUTE) return false;
+    return o->reserved0 == 0 && o->reserved1 == 0;
+}
+
+// A device-accessible buffer of at least `bytes` starting at p.  Plain host
+// memory is rejected; when the runtime knows the allocation's extent, the
+// buffer must lie inside it.
+bool buffer_ok(const void* p, size_t bytes) {
+    if (bytes == 0) return true;
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    std::memset(&at, 0, sizeof(at));
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged &&
+        !(at.type == hipMemoryTypeHost && at.devicePointer != nullptr))
+        return false;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess && base) {
+        const uintptr_t lo = reinterpret_cast<uintptr_t>(base), hi = lo + size;
+        const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+        if (a < lo || a + bytes > hi) return false;
+    } else {
+        (void)hipGetLastError();
+    }
+    return true;
+}
+
+l0_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return L0_OK;
+    if (e == hipErrorOutOfMemory) return L0_ERR_OOM;
+    return L0_ERR_HIP;
+}
+
+l0::MatrixView carve_matrix(char* base, int64_t n, int32_t m, int32_t d) {
+    const l0::MatrixBuffers b = l0::matrix_layout(n, m, d);
+    l0::MatrixView v{};
+    v.n = n;
+    v.m = m;
+    v.d = d;
+    v.ntiles = (n + l0::kTile - 1) / l0::kTile;
+    char* p = base;
+    v.soa = reinterpret_cast<int32_t*>(p);       p += b.soa;
+    v.row_off = reinterpret_cast<int32_t*>(p);   p += b.row_off;
+    v.deg = reinterpret_cast<int32_t*>(p);       p += b.deg;
+    v.bad_index = reinterpret_cast<int32_t*>(p);
+    return v;
+}
+
+void carve_solve(l0::SolveParams& q, char* base, int64_t n, int32_t m, int32_t d, int32_t max_iter) {
+    const l0::SolveBuffers b = l0::solve_layout(n, m, d, max_iter);
+    char* p = base;
+    q.ctrl = reinterpret_cast<l0::Ctrl*>(p);            p += b.ctrl;
+    q.tcount = reinterpret_cast<int32_t*>(p);
+    q.affc = q.tcount + (max_iter + 2);                  p += b.counters;
+    q.r = reinterpret_cast<double*>(p);                  p += b.r;
+    q.slot_cnt = reinterpret_cast<int32_t*>(p);          p += b.slot_cnt;
+    q.slot_sorted = reinterpret_cast<int32_t*>(p);       p += b.slot_sorted;
+    q.aff_flag = reinterpret_cast<int32_t*>(p);          p += b.aff_flag;
+    q.aff_list = reinterpret_cast<int32_t*>(p);          p += b.aff_list;
+    q.member = reinterpret_cast<uint32_t*>(p);           p += b.member;
+    q.slots = reinterpret_cast<int32_t*>(p);
+}
+
+l0_status run_solve(const l0::MatrixView& A, const double* y, double alpha, int32_t max_iter,
+                    double tol, double* x_out, const l0_opts* opts, l0_result* res,
+                    int32_t* iters_out, char* ws, hipStream_t stream) {
+    l0::SolveParams q{};
+    q.n = A.n;
+    q.m = A.m;
+    q.d = A.d;
+    q.ntiles = A.ntiles;
+    q.soa = A.soa;
+    q.row_off = A.row_off;
+    q.bad_index = A.bad_index;
+    q.y = y;
+    q.tol = tol;
+    q.a = static_cast<int32_t>(std::ceil(alpha));
+    q.max_iter = max_iter;
+    q.rule = opts ? opts->rule : L0_RULE_L0DEC;
+    q.tol_mode = opts ? opts->tol_mode : L0_TOL_RELATIVE;
+    q.x_init = opts ? opts->x_init : nullptr;
+    q.x = x_out;
+    q.trace = opts ? opts->trace : nullptr;
+    q.tsize = opts ? opts->tsize : nullptr;
+    q.res = res;
+    q.iters_out = iters_out;
+    carve_solve(q, ws, A.n, A.m, A.d, max_iter);
+    return from_hip(l0::launch_solve(q, stream));
+}
+
+bool common_buffers_ok(int64_t n, int32_t m, int32_t max_iter, const double* y, double* x_out,
+                       const l0_opts* opts) {
+    if (!buffer_ok(y, static_cast<size_t>(m) * sizeof(double))) return false;
+    if (!buffer_ok(x_out, static_cast<size_t>(n) * sizeof(double))) return false;
+    if (opts) {
+        if (opts->x_init && !buffer_ok(opts->x_init, static_cast<size_t>(n) * sizeof(double))) return false;
+        if (opts->trace && !buffer_ok(opts->trace, (static_cast<size_t>(max_iter) + 1) * sizeof(int32_t)))
+            return false;
+        if (opts->tsize && max_iter > 0 &&
+            !buffer_ok(opts->tsize, static_cast<size_t>(max_iter) * sizeof(int64_t)))
+            return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* l0_version(void) { return "l0decode 0.1 (gfx950)"; }
+
+const char* l0_status_string(int32_t code) {
+    switch (code) {
+        case 0: return "L0_OK / L0_CONVERGED";
+        case 1: return "L0_ERR_ARG / L0_STALLED";
+        case 2: return "L0_ERR_OOM / L0_MAX_ITER";
+        case 3: return "L0_ERR_HIP";
+        case 4: return "L0_ERR_WORKSPACE";
+        case L0_DEV_BAD_INDEX: return "L0_DEV_BAD_INDEX";
+        case L0_DEV_NONFINITE_Y: return "L0_DEV_NONFINITE_Y";
+        case L0_DEV_ABORTED: return "L0_DEV_ABORTED";
+        default: return "unknown";
+    }
+}
+
+size_t l0_workspace_bytes(int64_t n, int32_t m, int32_t d, int32_t max_iter) {
+    if (!sizes_ok(n, m, d) || max_iter < 0 || max_iter > kMaxIterCap) return 0;
+    return l0::matrix_layout(n, m, d).total + l0::solve_layout(n, m, d, max_iter).total;
+}
+
+l0_status l0_decode_ex(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y,
+                       double alpha, int32_t max_iter, double tol, double* x_out,
+                       const l0_opts* opts, l0_result* res_out, void* workspace,
+                       size_t ws_bytes, hipStream_t stream) {
+    if (!sizes_ok(n, m, d) || !solve_args_ok(alpha, d, max_iter, tol) || !opts_ok(opts)) return L0_ERR_ARG;
+    if (!buffer_ok(col_idx, static_cast<size_t>(n) * d * sizeof(int32_t))) return L0_ERR_ARG;
+    if (!common_buffers_ok(n, m, max_iter, y, x_out, opts)) return L0_ERR_ARG;
+    if (!buffer_ok(res_out, sizeof(l0_result))) return L0_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return L0_ERR_ARG;
+    const size_t need = l0_workspace_bytes(n, m, d, max_iter);
+    if (ws_bytes < need) return L0_ERR_WORKSPACE;
+    if (!buffer_ok(workspace, need)) return L0_ERR_ARG;
+    char* base = static_cast<char*>(workspace);
+    const l0::MatrixView A = carve_matrix(base, n, m, d);
+    l0_status st = from_hip(l0::launch_prepare(col_idx, A, 1, stream));
+    if (st != L0_OK) return st;
+    return run_solve(A, y, alpha, max_iter, tol, x_out, opts, res_out, nullptr,
+                     base + l0::matrix_layout(n, m, d).total, stream);
+}
+
+l0_status l0_decode(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y,
+                    double alpha, int32_t max_iter, double tol, double* x_out,
+                    int32_t* iters_out, hipStream_t stream) {
+    if (!sizes_ok(n, m, d) || !solve_args_ok(alpha, d, max_iter, tol)) return L0_ERR_ARG;
+    if (!buffer_ok(col_idx, static_cast<size_t>(n) * d * sizeof(int32_t))) return L0_ERR_ARG;
+    if (!common_buffers_ok(n, m, max_iter, y, x_out, nullptr)) return L0_ERR_ARG;
+    if (!buffer_ok(iters_out, sizeof(int32_t))) return L0_ERR_ARG;
+    const size_t mat = l0::matrix_layout(n, m, d).total;
+    const size_t need = mat + l0::solve_layout(n, m, d, max_iter).total + l0::align256(sizeof(l0_result));
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, need, stream);
+    if (e != hipSuccess) return from_hip(e);
+    char* base = static_cast<char*>(ws);
+    const l0::MatrixView A = carve_matrix(base, n, m, d);
+    l0_result* res = reinterpret_cast<l0_result*>(base + need - l0::align256(sizeof(l0_result)));
+    l0_status st = from_hip(l0::launch_prepare(col_idx, A, 1, stream));
+    if (st == L0_OK)
+        st = run_solve(A, y, alpha, max_iter, tol, x_out, nullptr, res, iters_out, base + mat, stream);
+    e = hipFreeAsync(ws, stream);
+    if (st == L0_OK && e != hipSuccess) st = from_hip(e);
+    return st;
+}
+
+l0_status l0_matrix_create(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, l0_matrix* out,
+                           hipStream_t stream) {
+    if (!out) return L0_ERR_ARG;
+    *out = nullptr;
+    if (!sizes_ok(n, m, d)) return L0_ERR_ARG;
+    if (!buffer_ok(col_idx, static_cast<size_t>(n) * d * sizeof(int32_t))) return L0_ERR_ARG;
+    l0_matrix h = new (std::nothrow) l0_matrix_s;
+    if (!h) return L0_ERR_OOM;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return L0_ERR_HIP;
+    }
+    hipError_t e = hipMalloc(&h->base, l0::matrix_layout(n, m, d).total);
+    if (e != hipSuccess) {
+        delete h;
+        return from_hip(e);
+    }
+    h->view = carve_matrix(static_cast<char*>(h->base), n, m, d);
+    l0_status st = from_hip(l0::launch_prepare(col_idx, h->view, 1, stream));
+    if (st != L0_OK) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(h->base);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return L0_OK;
+}
+
+l0_status l0_matrix_destroy(l0_matrix A) {
+    if (!A) return L0_OK;
+    hipError_t e = hipDeviceSynchronize();
+    hipError_t f = hipFree(A->base);
+    delete A;
+    return from_hip(e != hipSuccess ? e : f);
+}
+
+size_t l0_solve_workspace_bytes(l0_matrix A, int32_t max_iter) {
+    if (!A || max_iter < 0 || max_iter > kMaxIterCap) return 0;
+    return l0::solve_layout(A->view.n, A->view.m, A->view.d, max_iter).total;
+}
+
+l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter, double tol,
+                   double* x_out, const l0_opts* opts, l0_result* res_out, void* workspace,
+                   size_t ws_bytes, hipStream_t stream) {
+    if (!A || !solve_args_ok(alpha, A->view.d, max_iter, tol) || !opts_ok(opts)) return L0_ERR_ARG;
+    const int64_t n = A->view.n;
+    const int32_t m = A->view.m;
+    if (!common_buffers_ok(n, m, max_iter, y, x_out, opts)) return L0_ERR_ARG;
+    if (!buffer_ok(res_out, sizeof(l0_result))) return L0_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return L0_ERR_ARG;
+    const size_t need = l0_solve_workspace_bytes(A, max_iter);
+    if (ws_bytes < need) return L0_ERR_WORKSPACE;
+    if (!buffer_ok(workspace, need)) return L0_ERR_ARG;
+    return run_solve(A->view, y, alpha, max_iter, tol, x_out, opts, res_out, nullptr,
+                     static_cast<char*>(workspace), stream);
+}
+
+}  // extern "C"

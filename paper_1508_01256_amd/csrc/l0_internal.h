@@ -1,0 +1,101 @@
+// Internal declarations shared by the host API and the device code of the
+// Parallel-l0 decoder.  Not part of the public C-ABI (include/l0decode.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "l0decode.h"
+
+namespace l0 {
+
+constexpr int kDMin = 2;
+constexpr int kDMax = 20;
+constexpr int kTile = 256;          // columns per tile of the repacked index store
+constexpr int kBlock = 1024;        // threads per workgroup of the solve kernel
+constexpr int kWaves = kBlock / 64; // wavefronts per workgroup
+// Residual entries staged in LDS when 8*m fits under this (gfx950 has 160 KiB per CU).
+constexpr size_t kLdsRBytes = 152 * 1024;
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Device-resident prepared matrix (layout of the repacked column-index store):
+//   soa[(tile*d + t)*kTile + c] = row of column tile*kTile + c, t-th neighbour
+// (columns past n hold row 0 and are never scored); row_off[i] .. row_off[i+1]
+// is row i's capacity region in the per-row support lists (its degree in A).
+struct MatrixView {
+    int64_t n;
+    int32_t m;
+    int32_t d;
+    int64_t ntiles;
+    int32_t* soa;
+    int32_t* row_off;   // int32[m+1]
+    int32_t* deg;       // int32[m] scratch for the degree histogram
+    int32_t* bad_index; // int32[1]: nonzero when a row index was out of range
+};
+
+struct MatrixBuffers {
+    size_t soa, row_off, deg, flag, total;
+};
+MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d);
+
+// Control block at the start of the solve workspace (zeroed before each solve).
+struct Ctrl {
+    unsigned int bar;        // grid barrier arrivals (monotonic)
+    int abort;               // set when a barrier timed out
+    int err;                 // device-detected error outcome, 0 if none
+    int nnz;                 // running ||r||_0
+    unsigned long long maxabs_bits; // bits of max_i |y_i| (non-negative doubles order as integers)
+    int support;             // columns ever updated
+    int pad0;
+    long long updates;       // sum of |T| over iterations
+    int pad[8];
+};
+
+struct SolveBuffers {
+    size_t ctrl, counters, r, slot_cnt, slot_sorted, aff_flag, aff_list, member, slots, total;
+};
+SolveBuffers solve_layout(int64_t n, int32_t m, int32_t d, int32_t max_iter);
+
+struct SolveParams {
+    // problem
+    int64_t n;
+    int32_t m;
+    int32_t d;
+    int64_t ntiles;
+    const int32_t* soa;
+    const int32_t* row_off;
+    const int32_t* bad_index;
+    const double* y;
+    double tol;
+    int32_t a;          // ceil(alpha)
+    int32_t max_iter;
+    int32_t rule;
+    int32_t tol_mode;
+    const double* x_init;
+    // outputs
+    double* x;
+    int32_t* trace;
+    int64_t* tsize;
+    l0_result* res;
+    int32_t* iters_out;  // optional (plain l0_decode)
+    // workspace
+    Ctrl* ctrl;
+    int32_t* tcount;     // int32[max_iter+2]
+    int32_t* affc;       // int32[max_iter+2]
+    double* r;
+    int32_t* slot_cnt;
+    int32_t* slot_sorted;
+    int32_t* aff_flag;
+    int32_t* aff_list;
+    uint32_t* member;
+    int32_t* slots;
+};
+
+// Enqueue the matrix preparation (repack, range check, degree histogram, scan).
+hipError_t launch_prepare(const int32_t* col_idx, const MatrixView& A, int check, hipStream_t s);
+
+// Enqueue one solve (control reset + the persistent cooperative kernel).
+hipError_t launch_solve(const SolveParams& p, hipStream_t s);
+
+}  // namespace l0

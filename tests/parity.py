@@ -1,0 +1,70 @@
+"""Helpers for GPU-vs-oracle parity: run one instance through the HIP library
+(via the C-ABI binding) and through the CPU oracle, and compare."""
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+import paper_1508_01256_amd as l0
+
+RULE_MAP = {l0.L0_RULE_L0DEC: oracle.RULE_L0DEC, l0.L0_RULE_MODE: oracle.RULE_MODE}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def gpu_run(n, m, d, col, y, alpha, *, max_iter=100, tol=1e-10, rule=l0.L0_RULE_L0DEC,
+            x_init=None, tol_mode=l0.L0_TOL_RELATIVE):
+    colt = to_dev(col, torch.int32)
+    yt = to_dev(y, torch.float64)
+    xi = None if x_init is None else to_dev(x_init, torch.float64)
+    out = l0.decode(colt, yt, n, m, d, alpha, max_iter=max_iter, tol=tol, rule=rule, x_init=xi,
+                    tol_mode=tol_mode)
+    out["x"] = out["x"].cpu().numpy()
+    if "trace" in out:
+        out["trace"] = out["trace"].numpy()
+        out["tsize"] = out["tsize"].numpy()
+    return out
+
+
+def oracle_run(n, m, d, col, y, alpha, *, max_iter=100, tol=1e-10, rule=l0.L0_RULE_L0DEC,
+               x_init=None, tol_mode=l0.L0_TOL_RELATIVE):
+    if tol_mode == l0.L0_TOL_ABSOLUTE:
+        # the oracle takes a relative tolerance; convert (exact only when the
+        # division and multiplication round-trip, so tests use powers of two)
+        s = float(np.max(np.abs(y)))
+        tol = tol / s if s > 0 else tol
+    return oracle.parallel_l0(n, m, d, col, y, alpha, max_iter=max_iter, tol=tol,
+                              rule=RULE_MAP[rule], x_init=x_init)
+
+
+def assert_parity(g, o, *, label=""):
+    """Support, iteration count, outcome and ||r||_0 trace bitwise; x_hat
+    bitwise (which implies the 1e-12 relative value tolerance)."""
+    assert g["outcome"] == o["outcome"], (label, g["outcome"], o["outcome"])
+    assert g["iters"] == o["iters"], (label, g["iters"], o["iters"])
+    assert g["trace"].tolist() == o["trace"].tolist(), (label, g["trace"], o["trace"])
+    assert g["tsize"].tolist() == o["tsize"].tolist(), (label, g["tsize"], o["tsize"])
+    gx, ox = g["x"], o["x"]
+    assert np.array_equal(gx != 0, ox != 0), label
+    scale = max(1.0, float(np.max(np.abs(ox)))) if ox.size else 1.0
+    assert float(np.max(np.abs(gx - ox), initial=0.0)) <= 1e-12 * scale, label
+    assert np.array_equal(gx.view(np.int64), ox.view(np.int64)), (label, "x_hat not bitwise equal")
+    assert g["final_nnz"] == o["trace"][-1], label
+
+
+def run_both(inst_or_arrays, **kw):
+    if hasattr(inst_or_arrays, "col_idx"):
+        i = inst_or_arrays
+        args = (i.n, i.m, i.d, i.col_idx, i.y, kw.pop("alpha", i.alpha))
+    else:
+        args = inst_or_arrays
+    g = gpu_run(*args, **kw)
+    o = oracle_run(*args, **kw)
+    return g, o

@@ -1,0 +1,85 @@
+"""The C-ABI library: it is built, loads, exports every entry point declared
+in include/*.h, and rejects invalid arguments on the host before any device
+work (these calls need no GPU)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+import paper_1508_01256_amd as l0
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"^[A-Za-z_][\w\s\*]*?\b(l0_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_builds_and_loads():
+    assert os.path.exists(l0.LIB_PATH), "run __graft_entry__.build() first"
+    L = l0.lib()
+    assert l0.l0_version().startswith("l0decode")
+
+
+def test_every_declared_symbol_is_exported():
+    decl = declared_functions()
+    assert set(decl) == set(l0.EXPORTED), decl
+    L = ctypes.CDLL(l0.LIB_PATH)
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_workspace_bytes_host_only():
+    assert l0.l0_workspace_bytes(4096, 512, 7, 100) > 4096 * 7 * 4 * 2
+    # invalid shapes give 0
+    for args in [(0, 512, 7, 10), (4096, 0, 7, 10), (4096, 512, 1, 10), (4096, 512, 21, 10),
+                 (10, 5, 7, 10), (4096, 512, 7, -1), (1 << 31, 512, 7, 10)]:
+        assert l0.l0_workspace_bytes(*args) == 0, args
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=0), dict(m=0), dict(d=1), dict(d=21), dict(d=9, m=8), dict(alpha=1.0),
+    dict(alpha=0.5), dict(alpha=7.5), dict(alpha=float("nan")), dict(max_iter=-1),
+    dict(tol=-1e-3), dict(tol=float("inf")), dict(tol=float("nan")),
+])
+def test_argument_errors_are_rejected_before_device_work(bad):
+    a = dict(n=4096, m=512, d=7, alpha=4.0, max_iter=10, tol=1e-10)
+    a.update(bad)
+    L = l0.lib()
+    # null buffers are never dereferenced: the scalar checks come first
+    st = L.l0_decode(None, a["n"], a["m"], a["d"], None, a["alpha"], a["max_iter"], a["tol"], None,
+                     None, None)
+    assert st == l0.L0_ERR_ARG
+    st = L.l0_decode_ex(None, a["n"], a["m"], a["d"], None, a["alpha"], a["max_iter"], a["tol"],
+                        None, None, None, None, 0, None)
+    assert st == l0.L0_ERR_ARG
+
+
+def test_bad_options_and_handles():
+    L = l0.lib()
+    o = l0.l0_opts(rule=5)
+    st = L.l0_decode_ex(None, 4096, 512, 7, None, 4.0, 10, 1e-10, None, ctypes.byref(o), None, None,
+                        0, None)
+    assert st == l0.L0_ERR_ARG
+    o = l0.l0_opts(tol_mode=3)
+    assert L.l0_decode_ex(None, 4096, 512, 7, None, 4.0, 10, 1e-10, None, ctypes.byref(o), None,
+                          None, 0, None) == l0.L0_ERR_ARG
+    o = l0.l0_opts(reserved0=1)
+    assert L.l0_decode_ex(None, 4096, 512, 7, None, 4.0, 10, 1e-10, None, ctypes.byref(o), None,
+                          None, 0, None) == l0.L0_ERR_ARG
+    assert L.l0_matrix_create(None, 4096, 512, 7, None, None) == l0.L0_ERR_ARG
+    assert L.l0_solve(None, None, 4.0, 10, 1e-10, None, None, None, None, 0, None) == l0.L0_ERR_ARG
+    assert L.l0_solve_workspace_bytes(None, 10) == 0
+    assert L.l0_matrix_destroy(None) == l0.L0_OK
+
+
+def test_status_strings():
+    assert "CONVERGED" in l0.l0_status_string(0)
+    assert l0.l0_status_string(l0.L0_DEV_BAD_INDEX) == "L0_DEV_BAD_INDEX"
