@@ -56,9 +56,15 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
+def passes_of(iters, outcome):
+    """Vote passes in a solve: one per iteration, plus the final one that
+    finds no column to update when the run stalls."""
+    return iters + (1 if outcome == 1 else 0)
+
+
 def algorithmic_bytes(n, m, d, iters, outcome, tsizes):
     """Bytes the method must move in one solve launch (see module doc)."""
-    passes = iters + (1 if outcome == 1 else 0)  # a stalled run votes once more, finding T empty
+    passes = passes_of(iters, outcome)
     b = 8 * n                      # x_hat = 0
     b += 16 * m                    # r = y (read y, write r)
     b += passes * 4 * n * d        # column-index stream per vote pass
@@ -75,6 +81,9 @@ def main():
     ap.add_argument("--repeats", type=int, default=30, help="l0_solve launches timed for the roofline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--kind", choices=["normal", "pm1"], default="normal")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 launches) to calibrate "
+                         "rocprofv3 byte counters, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the decoder has no "
@@ -88,6 +97,15 @@ def main():
     import paper_1508_01256_amd as l0
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.ones(args.calibrate_copy << 18, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes_each_way": a.numel() * 4, "launches": 3}))
+        return
     kind = gen.VALUES_NORMAL if args.kind == "normal" else gen.VALUES_PM1
     t0 = time.time()
     inst = gen.single_workload("n2^24", 0, kind=kind)
@@ -149,6 +167,20 @@ def main():
     s_iters, s_outcome = (int(v) for v in rr[:1].view(torch.int32).tolist())
     assert (s_iters, s_outcome) == (iters, outcome)
     assert torch.equal(xs, x), "prepared-matrix solve differs from the one-shot decode"
+    # one more solve with the in-kernel phase timeline (device wall clock, 100 MHz)
+    tl = torch.zeros(6 * max_iter + 16, dtype=torch.int64, device="cuda")
+    A.solve_async(y, alpha, max_iter=max_iter, tol=tol, x=xs, res=rs, timeline=tl)
+    torch.cuda.synchronize()
+    tlv = tl.cpu().tolist()
+    nb = 3 + 2 * iters + (1 if outcome == 1 else 0)
+    phases_us = [round((tlv[i + 1] - tlv[i]) / 100.0, 1) for i in range(nb - 1) if tlv[i + 1] > 0]
+    sub = []
+    for l in range(passes_of(iters, outcome)):
+        b = 3 * max_iter + 8 + 3 * l
+        if tlv[b + 2] > 0:
+            sub.append([round((tlv[b + k] - tlv[b + k - 1 if k else b]) / 100.0, 1) for k in range(3)])
+    print(f"[bench] phase timeline (us, between grid barriers): {phases_us}", file=sys.stderr, flush=True)
+    print(f"[bench] vote sub-phases (us since stage/stream/queue): {sub}", file=sys.stderr, flush=True)
     ts = tsize[:iters].cpu().tolist()
     tr = trace[: iters + 1].cpu().tolist()
     bytes_launch, passes = algorithmic_bytes(n, m, d, iters, outcome, ts)
@@ -202,7 +234,8 @@ def main():
                    "solve_prepared_min_ms": round(min(solve_ms), 4),
                    "per_vote_pass_us": round(solve_avg * 1e3 / max(passes, 1), 2),
                    "vote_bytes_per_pass": vote_bytes, "prepare_ms": round(prep_ms, 3),
-                   "solves_per_s_prepared": round(1e3 / solve_avg, 3)},
+                   "solves_per_s_prepared": round(1e3 / solve_avg, 3),
+                   "phase_us": phases_us},
     }
     print(json.dumps(out), flush=True)
 

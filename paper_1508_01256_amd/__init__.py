@@ -52,7 +52,7 @@ class l0_opts(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
                 ("x_init", ctypes.c_void_p), ("trace", ctypes.c_void_p),
-                ("tsize", ctypes.c_void_p)]
+                ("tsize", ctypes.c_void_p), ("timeline", ctypes.c_void_p)]
 
 
 _lib = None
@@ -117,10 +117,11 @@ def l0_workspace_bytes(n, m, d, max_iter) -> int:
     return lib().l0_workspace_bytes(n, m, d, max_iter)
 
 
-def _opts(rule, tol_mode, x_init, trace, tsize):
+def _opts(rule, tol_mode, x_init, trace, tsize, timeline=None):
     return l0_opts(rule, tol_mode, 0, 0, None if x_init is None else x_init.data_ptr(),
                    None if trace is None else trace.data_ptr(),
-                   None if tsize is None else tsize.data_ptr())
+                   None if tsize is None else tsize.data_ptr(),
+                   None if timeline is None else timeline.data_ptr())
 
 
 def l0_decode_ex(col_idx, n, m, d, y, alpha, max_iter, tol, x_out, opts, res_out, workspace) -> int:
@@ -207,12 +208,12 @@ class Matrix:
 
     def solve_async(self, y, alpha, *, max_iter=100, tol=1e-10, rule=L0_RULE_L0DEC,
                     tol_mode=L0_TOL_RELATIVE, x=None, res=None, trace=None, tsize=None,
-                    x_init=None, workspace=None):
+                    x_init=None, workspace=None, timeline=None):
         """Enqueue one solve on the current stream; returns (x, res)."""
         x = torch.empty(self.n, dtype=torch.float64, device=y.device) if x is None else x
         res = new_result(y.device) if res is None else res
         ws = self.workspace(max_iter) if workspace is None else workspace
-        o = _opts(rule, tol_mode, x_init, trace, tsize)
+        o = _opts(rule, tol_mode, x_init, trace, tsize, timeline)
         _check(l0_solve(self.handle, y, alpha, max_iter, tol, x, o, res, ws), "l0_solve")
         return x, res
 

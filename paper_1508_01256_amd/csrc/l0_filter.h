@@ -1,0 +1,184 @@
+// Column scoring shared by the decoder's kernels: the exact score of one
+// column (eq. (selection_l0)) and the bucket-word filter that lets the
+// streaming vote skip the exact score for columns that cannot be selected.
+// Host-callable as well, so the filter's exactness can be tested on the CPU.
+#pragma once
+
+#include <cmath>
+#include <climits>
+#include <cstdint>
+
+#ifdef __HIPCC__
+#include <hip/hip_runtime.h>
+#define L0_HD __host__ __device__ __forceinline__
+#else
+#define L0_HD
+#endif
+
+namespace l0 {
+
+// Scoring rules (same values as l0_rule in l0decode.h).
+constexpr int kRuleL0dec = 0;
+constexpr int kRuleMode = 1;
+
+// The score itself, by its definition, on the column's gathered residual
+// values v[0..D): for every nonzero candidate v[t], c counts the entries u with
+// |v[u] - v[t]| <= tau; the l0-decrease is c - z with z the number of zero
+// entries (the frequency rule scores c).  Best score wins, ties go to the
+// smallest value.  Returns true (and omega) when the best score reaches a.
+template <int D>
+L0_HD bool exact_score(const double (&v)[D], double tau, int rule, int a,
+                                            double& omega) {
+    int z = 0;
+#pragma unroll
+    for (int u = 0; u < D; ++u) z += !(std::fabs(v[u]) > tau);
+    int top = INT_MIN;
+    double w = 0.0;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        if (!(std::fabs(v[t]) > tau)) continue;
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < D; ++u) cnt += !(std::fabs(v[u] - v[t]) > tau);
+        const int score = (rule == kRuleMode) ? cnt : cnt - z;
+        if (top == INT_MIN || score > top || (score == top && v[t] < w)) {
+            top = score;
+            w = v[t];
+        }
+    }
+    omega = w;
+    return top != INT_MIN && top >= a;
+}
+
+// ---------------------------------------------------------------------------
+// row bucket words: a cheap, exact necessary condition for selection
+// ---------------------------------------------------------------------------
+//
+// Each row i carries a 32-bit word: bit 31 marks a zero entry (|r_i| <= tau);
+// bits 0..30 are hashed buckets of the value r_i on a grid of width W, a power
+// of two with W >= 16 tau.  A row also marks the neighbouring bucket when r_i
+// lies within W/8 of a bucket edge.  If |r_u - r_t| <= tau (up to one
+// rounding), then r_u and r_t are either in one bucket or straddle an edge
+// within tau <= W/16 of both, so r_u carries the bucket bit of r_t.  Hence for
+// any candidate t, the number of the column's words holding t's bucket bit is
+// at least c_t, and a column can only be selected when some bucket bit is set
+// in at least a + z of its words (a for the frequency rule).  Columns passing
+// that test are scored exactly by exact_score() on FP64 values.
+
+constexpr double kEdge = 0.125;  // W/8 band at each bucket edge
+constexpr uint32_t kZeroBit = 0x80000000u;
+constexpr uint32_t kBucketBits = 0x7FFFFFFFu;
+
+L0_HD uint32_t bucket_bit(double b) {
+    // b is an integer-valued double; +0.0 folds a negative zero.
+    uint64_t h = __builtin_bit_cast(uint64_t, b + 0.0);
+    h *= 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
+    h *= 0xBF58476D1CE4E5B9ull;
+    return 1u << static_cast<uint32_t>((h >> 32) % 31u);
+}
+
+L0_HD uint32_t row_word(double r, double tau, double inv_w) {
+    uint32_t w = (std::fabs(r) > tau) ? 0u : kZeroBit;
+    const double q = r * inv_w;  // exact: inv_w is a power of two
+    if (!(std::fabs(q) < 0x1p51)) return w | kBucketBits;  // huge or non-finite: every bucket
+    const double b = std::floor(q);
+    const double f = q - b;      // exact, in [0, 1)
+    w |= bucket_bit(b);
+    if (f < kEdge) w |= bucket_bit(b - 1.0);
+    if (f > 1.0 - kEdge) w |= bucket_bit(b + 1.0);
+    return w;
+}
+
+// Bucket width: the smallest power of two >= 16 tau (tau > 0), or a grid
+// fine relative to max |y| when tau = 0 (exact equality needs no width).
+L0_HD double bucket_width(double tau, double ymax) {
+    double base = tau > 0.0 ? 16.0 * tau : ymax * 0x1p-44;
+    if (!(base > 0x1p-1000)) base = 0x1p-1000;
+    if (!(base < 0x1p1000)) base = 0x1p1000;
+    int e = 0;
+    (void)std::frexp(base, &e);  // base = f * 2^e, f in [0.5, 1)
+    return std::ldexp(1.0, e);
+}
+
+// Bit-sliced population count of D words: c[k] holds bit k of the per-bit-
+// position count.  Full adders (xor / majority) for the common degrees, a
+// ripple-carry accumulation otherwise.
+template <int D>
+struct Levels {
+    static constexpr int L = D >= 16 ? 5 : D >= 8 ? 4 : D >= 4 ? 3 : D >= 2 ? 2 : 1;
+};
+
+L0_HD void full_add(uint32_t a, uint32_t b, uint32_t c, uint32_t& s, uint32_t& cy) {
+    const uint32_t x = a ^ b;
+    s = x ^ c;
+    cy = (x & c) | (~x & a);
+}
+
+template <int D>
+L0_HD void bit_count(const uint32_t (&w)[D], uint32_t (&c)[Levels<D>::L]) {
+    constexpr int L = Levels<D>::L;
+    if constexpr (D == 7) {
+        uint32_t s1, c1, s2, c2, c3, c4;
+        full_add(w[0], w[1], w[2], s1, c1);
+        full_add(w[3], w[4], w[5], s2, c2);
+        full_add(s1, s2, w[6], c[0], c3);
+        full_add(c1, c2, c3, c[1], c4);
+        c[2] = c4;
+    } else if constexpr (D == 5) {
+        uint32_t s1, c1, c2;
+        full_add(w[0], w[1], w[2], s1, c1);
+        full_add(s1, w[3], w[4], c[0], c2);
+        c[1] = c1 ^ c2;
+        c[2] = c1 & c2;
+    } else if constexpr (D == 9) {
+        uint32_t s1, c1, s2, c2, s3, c3, c4, t1, c5, c6;
+        full_add(w[0], w[1], w[2], s1, c1);
+        full_add(w[3], w[4], w[5], s2, c2);
+        full_add(w[6], w[7], w[8], s3, c3);
+        full_add(s1, s2, s3, c[0], c4);
+        full_add(c1, c2, c3, t1, c5);
+        c[1] = t1 ^ c4;
+        c6 = t1 & c4;
+        c[2] = c5 ^ c6;
+        c[3] = c5 & c6;
+    } else {
+#pragma unroll
+        for (int k = 0; k < L; ++k) c[k] = 0u;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            uint32_t carry = w[i];
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const uint32_t t = c[k] & carry;
+                c[k] ^= carry;
+                carry = t;
+            }
+        }
+    }
+}
+
+// True when some bucket bit is set in at least a + z words (a words for the
+// frequency rule), z being the count of zero entries (bit 31).
+template <int D>
+L0_HD bool bucket_filter(const uint32_t (&w)[D], int a, int rule) {
+    constexpr int L = Levels<D>::L;
+    uint32_t c[L];
+    bit_count<D>(w, c);
+    int z = 0;
+#pragma unroll
+    for (int k = 0; k < L; ++k) z |= static_cast<int>(c[k] >> 31) << k;
+    const int need = a + (rule == kRuleL0dec ? z : 0);
+    if (need > D) return false;
+    uint32_t ge = 0u, eq = 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = L - 1; k >= 0; --k) {
+        const uint32_t tb = ((need >> k) & 1) ? 0xFFFFFFFFu : 0u;
+        ge |= eq & c[k] & ~tb;
+        eq &= ~(c[k] ^ tb);
+    }
+    return ((ge | eq) & kBucketBits) != 0u;
+}
+
+
+}  // namespace l0

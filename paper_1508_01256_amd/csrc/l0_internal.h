@@ -14,8 +14,9 @@ constexpr int kDMax = 20;
 constexpr int kTile = 256;          // columns per tile of the repacked index store
 constexpr int kBlock = 1024;        // threads per workgroup of the solve kernel
 constexpr int kWaves = kBlock / 64; // wavefronts per workgroup
-// Residual entries staged in LDS when 8*m fits under this (gfx950 has 160 KiB per CU).
-constexpr size_t kLdsRBytes = 152 * 1024;
+// Row bucket words staged in LDS when 4*m fits under this (gfx950 has 160 KiB
+// per CU; the rest holds the per-workgroup queue and reduction scratch).
+constexpr size_t kLdsWordBytes = 144 * 1024;
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -40,8 +41,10 @@ struct MatrixBuffers {
 MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d);
 
 // Control block at the start of the solve workspace (zeroed before each solve).
+constexpr int kMaxXcc = 16;     // XCDs (accelerator complex dies) a device may have
+constexpr int kXccStride = 32;  // per-XCD counters sit 128 bytes apart
 struct Ctrl {
-    unsigned int bar;        // grid barrier arrivals (monotonic)
+    unsigned int bar;        // grid barrier: arrivals of per-XCD leaders (monotonic)
     int abort;               // set when a barrier timed out
     int err;                 // device-detected error outcome, 0 if none
     int nnz;                 // running ||r||_0
@@ -49,11 +52,16 @@ struct Ctrl {
     int support;             // columns ever updated
     int pad0;
     long long updates;       // sum of |T| over iterations
-    int pad[8];
+    unsigned int start;      // start-up arrivals (every workgroup once)
+    int pad[23];
+    unsigned int xcount[kMaxXcc];                 // workgroups resident on each XCD
+    unsigned int xarrive[kMaxXcc * kXccStride];   // per-XCD barrier arrivals (monotonic)
+    unsigned int xrelease[kMaxXcc * kXccStride];  // per-XCD release epoch
 };
 
 struct SolveBuffers {
-    size_t ctrl, counters, r, slot_cnt, slot_sorted, aff_flag, aff_list, member, slots, total;
+    size_t ctrl, counters, r, rword, slot_cnt, slot_sorted, aff_flag, aff_list, member, slots,
+        overflow, total;
 };
 SolveBuffers solve_layout(int64_t n, int32_t m, int32_t d, int32_t max_iter);
 
@@ -77,19 +85,23 @@ struct SolveParams {
     double* x;
     int32_t* trace;
     int64_t* tsize;
+    int64_t* timeline;   // optional: wall clock at start and after each grid barrier
     l0_result* res;
     int32_t* iters_out;  // optional (plain l0_decode)
     // workspace
     Ctrl* ctrl;
     int32_t* tcount;     // int32[max_iter+2]
     int32_t* affc;       // int32[max_iter+2]
+    int32_t* ovc;        // int32[max_iter+2]: columns in the overflow queue per iteration
     double* r;
+    uint32_t* rword;     // uint32[m]: bucket word of each residual entry
     int32_t* slot_cnt;
     int32_t* slot_sorted;
     int32_t* aff_flag;
     int32_t* aff_list;
     uint32_t* member;
     int32_t* slots;
+    int32_t* overflow;   // int32[n]: columns that passed the filter beyond the LDS queues
 };
 
 // Enqueue the matrix preparation (repack, range check, degree histogram, scan).

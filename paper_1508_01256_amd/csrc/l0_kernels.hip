@@ -19,6 +19,9 @@
 #include <climits>
 
 #include "l0_internal.h"
+#include "l0_filter.h"
+
+static_assert(l0::kRuleL0dec == L0_RULE_L0DEC && l0::kRuleMode == L0_RULE_MODE, "rule codes");
 
 namespace l0 {
 
@@ -30,31 +33,95 @@ __device__ __forceinline__ int ld_relaxed(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier.  Thread 0 of each workgroup publishes its phase's writes
-// (release), arrives on a monotonic counter and waits for all workgroups
-// (acquire).  A wait longer than `limit` wall-clock ticks raises the abort
-// flag instead of spinning forever; every workgroup then leaves the kernel.
-__device__ bool grid_sync(Ctrl* c, unsigned& epoch, uint64_t limit) {
-    __shared__ int s_ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        epoch += 1;
-        const unsigned target = epoch * gridDim.x;
-        __threadfence();
-        __hip_atomic_fetch_add(&c->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        int ok = 1;
-        const uint64_t t0 = wall_clock64();
-        while (__hip_atomic_load(&c->bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (ld_relaxed(&c->abort)) { ok = 0; break; }
-            if (wall_clock64() - t0 > limit) {
-                __hip_atomic_store(&c->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
+// Which XCD (accelerator complex die) this workgroup runs on, from the
+// hardware XCC_ID register.
+__device__ __forceinline__ unsigned xcc_id() {
+    return static_cast<unsigned>(__builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11))) & 0xFu;
+}
+
+// Bounded wait on a monotonic counter with relaxed loads.  Returns false on
+// the abort flag or after `limit` wall-clock ticks (then raising the flag).
+__device__ __forceinline__ bool wait_at_least(unsigned* p, unsigned target, Ctrl* c, uint64_t limit) {
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (ld_relaxed(&c->abort)) return false;
+        if (wall_clock64() - t0 > limit) {
+            __hip_atomic_store(&c->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
         }
-        __threadfence();
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+// Where this workgroup sits for the grid barrier.
+struct BarrierSite {
+    unsigned xcc;     // its XCD
+    unsigned nx;      // workgroups on that XCD
+    unsigned nxcc;    // XCDs with at least one workgroup
+    unsigned epoch;   // barriers passed
+};
+
+// Start-up: every workgroup records its XCD, then waits (relaxed) for all to
+// have done so; the counts are final afterwards.
+__device__ bool barrier_setup(Ctrl* c, BarrierSite& b, uint64_t limit) {
+    __shared__ unsigned s_site[3];
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        const unsigned x = xcc_id();
+        __hip_atomic_fetch_add(&c->xcount[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&c->start, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int ok = wait_at_least(&c->start, gridDim.x, c, limit) ? 1 : 0;
+        unsigned nx = 0, nxcc = 0;
+        for (int i = 0; i < kMaxXcc; ++i) {
+            const unsigned v = __hip_atomic_load(&c->xcount[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            nxcc += v != 0;
+            if (i == static_cast<int>(x)) nx = v;
+        }
+        s_site[0] = x;
+        s_site[1] = nx;
+        s_site[2] = nxcc;
         s_ok = ok;
+    }
+    __syncthreads();
+    b.xcc = s_site[0];
+    b.nx = s_site[1];
+    b.nxcc = s_site[2];
+    b.epoch = 0;
+    return s_ok != 0;
+}
+
+// Grid barrier, hierarchical over XCDs.  Each workgroup drains its own memory
+// operations (so its stores sit in its XCD's L2) and arrives on its XCD's
+// counter.  The last arriver of each XCD writes that L2 back once (agent-scope
+// release), arrives on the grid counter, waits for every XCD, invalidates its
+// caches (agent-scope acquire) and releases its XCD; the other workgroups wait
+// for that and acquire.  One L2 writeback per XCD instead of one per
+// workgroup; polling uses relaxed loads, which leave the L2 alone.  A wait
+// longer than `limit` raises the abort flag and every workgroup leaves the
+// kernel.  With a timeline, workgroup 0 stamps the wall clock.
+__device__ bool grid_sync(Ctrl* c, BarrierSite& b, uint64_t limit, int64_t* timeline = nullptr) {
+    __shared__ int s_ok;
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this thread's loads and stores are done
+    __syncthreads();
+    b.epoch += 1;
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned* xa = &c->xarrive[b.xcc * kXccStride];
+        unsigned* xr = &c->xrelease[b.xcc * kXccStride];
+        const unsigned old = __hip_atomic_fetch_add(xa, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == b.epoch * b.nx) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(&c->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = wait_at_least(&c->bar, b.epoch * b.nxcc, c, limit) ? 1 : 0;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(xr, b.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = wait_at_least(xr, b.epoch, c, limit) ? 1 : 0;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        s_ok = ok;
+        if (timeline && blockIdx.x == 0) timeline[b.epoch] = static_cast<int64_t>(wall_clock64());
     }
     __syncthreads();
     return s_ok != 0;
@@ -82,12 +149,6 @@ __device__ __forceinline__ int wave_count(bool pred) {
     return __popcll(__ballot(pred));
 }
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ int comp(const v4i& q, int c) {
-    return c == 0 ? q.x : c == 1 ? q.y : c == 2 ? q.z : q.w;
-}
-
 __device__ __forceinline__ int64_t soa_index(int64_t j, int t, int d) {
     return ((j / kTile) * d + t) * kTile + (j % kTile);
 }
@@ -103,93 +164,8 @@ __device__ void write_result(const SolveParams& p, int iters, int outcome, int n
 }
 
 // ---------------------------------------------------------------------------
-// the score of one column (eq. (selection_l0)) on its gathered values v[0..D)
+// the score of one column (eq. (selection_l0))
 // ---------------------------------------------------------------------------
-
-// Exact bound test.  With z zeros (|v| <= tau) a candidate's decrease is
-// c - z where c counts entries within tau of it.  A zero entry can only be
-// within tau of a candidate whose magnitude is at most t2 (~2 tau); without
-// such tiny candidates c <= number of nonzeros, otherwise c <= D.  Returns
-// true when no candidate can reach a.
-template <int D>
-__device__ __forceinline__ bool bound_rejects(const double (&v)[D], double tau, double t2, int a,
-                                              int rule) {
-    int nzc = 0, tiny = 0;
-#pragma unroll
-    for (int t = 0; t < D; ++t) {
-        const double av = fabs(v[t]);
-        const bool nz = av > tau;
-        nzc += nz;
-        tiny += nz && !(av > t2);
-    }
-    const int z = D - nzc;
-    const int bound = (tiny ? D : nzc) - (rule == L0_RULE_L0DEC ? z : 0);
-    return bound < a;
-}
-
-// Sorting network (odd-even transposition) on D values.
-template <int D>
-__device__ __forceinline__ void sort_values(double (&s)[D]) {
-#pragma unroll
-    for (int round = 0; round < D; ++round) {
-#pragma unroll
-        for (int i = round & 1; i + 1 < D; i += 2) {
-            const double lo = __builtin_fmin(s[i], s[i + 1]);
-            const double hi = __builtin_fmax(s[i], s[i + 1]);
-            s[i] = lo;
-            s[i + 1] = hi;
-        }
-    }
-}
-
-// Necessary condition for a candidate with c >= Q: its entries within tau lie
-// in a window of width <= 2 tau (up to one rounding each), i.e. Q consecutive
-// sorted values span at most t2.
-template <int D, int Q>
-__device__ __forceinline__ bool window_q(const double (&s)[D], double t2) {
-    bool ok = false;
-#pragma unroll
-    for (int i = 0; i + Q - 1 < D; ++i) ok |= (s[i + Q - 1] - s[i] <= t2);
-    return ok;
-}
-
-template <int D, int Q = 2>
-__device__ __forceinline__ bool window_pass(const double (&s)[D], int a, double t2) {
-    if constexpr (Q > D) {
-        return true;
-    } else {
-        if (a <= Q) return window_q<D, Q>(s, t2);
-        return window_pass<D, Q + 1>(s, a, t2);
-    }
-}
-
-// The score itself, by its definition: for every nonzero candidate v[t],
-// c counts the entries u with |v[u] - v[t]| <= tau; the l0-decrease is c - z
-// (the frequency rule scores c).  Best score wins, ties go to the smallest
-// value.  Returns true (and omega) when the best score reaches a.
-template <int D>
-__device__ __forceinline__ bool exact_score(const double (&v)[D], double tau, int rule, int a,
-                                            double& omega) {
-    int z = 0;
-#pragma unroll
-    for (int u = 0; u < D; ++u) z += !(fabs(v[u]) > tau);
-    int top = INT_MIN;
-    double w = 0.0;
-#pragma unroll
-    for (int t = 0; t < D; ++t) {
-        if (!(fabs(v[t]) > tau)) continue;
-        int cnt = 0;
-#pragma unroll
-        for (int u = 0; u < D; ++u) cnt += !(fabs(v[u] - v[t]) > tau);
-        const int score = (rule == L0_RULE_MODE) ? cnt : cnt - z;
-        if (top == INT_MIN || score > top || (score == top && v[t] < w)) {
-            top = score;
-            w = v[t];
-        }
-    }
-    omega = w;
-    return top != INT_MIN && top >= a;
-}
 
 template <int D>
 __device__ void apply_update(const SolveParams& p, int l, int64_t j, double w, const int (&rows)[D]) {
@@ -213,38 +189,93 @@ __device__ void apply_update(const SolveParams& p, int l, int64_t j, double w, c
     }
 }
 
-// Vote phase: each wave takes tiles of kTile columns; lane L holds columns
-// 4L..4L+3 of the tile, loading one 16-byte chunk per neighbour plane.
-template <int D, bool RL>
-__device__ void vote_phase(const SolveParams& p, int l, double tau, double t2, const double* lds_r) {
-    const int lane = threadIdx.x & 63;
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * kWaves;
-    const v4i* soa4 = reinterpret_cast<const v4i*>(p.soa);
-    for (int64_t tile = static_cast<int64_t>(blockIdx.x) * kWaves + (threadIdx.x >> 6);
-         tile < p.ntiles; tile += nw) {
-        v4i idx[D];
+// Exact scoring of one column that passed the bucket filter: its rows come
+// from the repacked index store, its values from the FP64 residual.
+template <int D>
+__device__ void score_exact(const SolveParams& p, int l, int64_t j, double tau) {
+    int rows[D];
+    double v[D];
 #pragma unroll
-        for (int t = 0; t < D; ++t) idx[t] = __builtin_nontemporal_load(&soa4[(tile * D + t) * 64 + lane]);
+    for (int t = 0; t < D; ++t) {
+        rows[t] = p.soa[soa_index(j, t, D)];
+        v[t] = p.r[rows[t]];
+    }
+    double w;
+    if (exact_score<D>(v, tau, p.rule, p.a, w)) apply_update<D>(p, l, j, w, rows);
+}
+
+constexpr int kQueue = 2048;  // per-workgroup queue of columns passing the filter
+
+// Rows of the 64 columns of chunk g (columns 64g .. 64g+63), one per lane:
+// the chunk is a quarter of a tile, so each neighbour plane is one coalesced
+// 256-byte load.  Offsets fit 32 bits (n*d < 2^31), which keeps one base
+// register pair for the whole stream.
+template <int D>
+__device__ __forceinline__ void load_chunk(const int32_t* __restrict__ soa, uint32_t g, uint32_t lane,
+                                           int (&rows)[D]) {
+    const uint32_t base = (g >> 2) * (D * kTile) + (g & 3u) * 64u + lane;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int64_t j = tile * kTile + lane * 4 + c;
-            int rows[D];
-            double v[D];
+    for (int t = 0; t < D; ++t) rows[t] = __builtin_nontemporal_load(soa + (base + t * kTile));
+}
+
+// Vote phase: waves stride over 64-column chunks, prefetching the next
+// chunk's row indices while the current chunk gathers its rows' bucket words
+// (from LDS when staged) and runs the bucket filter.  Columns passing it are
+// compacted per wave into an LDS queue (a global queue takes any overflow)
+// and scored exactly once the chunks are done.
+template <int D, bool WL>
+__device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32_t* lds_w,
+                           int* q_items, int* q_count) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t nchunks = static_cast<uint32_t>(p.ntiles * (kTile / 64));
+    const uint32_t stride = gridDim.x * kWaves;
+    const uint32_t n = static_cast<uint32_t>(p.n);
+    const int a = p.a, rule = p.rule;
+    const int32_t* __restrict__ soa = p.soa;
+    const uint32_t* __restrict__ words = WL ? lds_w : p.rword;
+    uint32_t g = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    int cur[D];
 #pragma unroll
-            for (int t = 0; t < D; ++t) {
-                rows[t] = comp(idx[t], c);
-                v[t] = RL ? lds_r[rows[t]] : p.r[rows[t]];
+    for (int t = 0; t < D; ++t) cur[t] = 0;
+    if (g < nchunks) load_chunk<D>(soa, g, lane, cur);
+    for (; g < nchunks; g += stride) {
+        int nxt[D];
+#pragma unroll
+        for (int t = 0; t < D; ++t) nxt[t] = 0;
+        if (g + stride < nchunks) load_chunk<D>(soa, g + stride, lane, nxt);
+        uint32_t w[D];
+#pragma unroll
+        for (int t = 0; t < D; ++t) w[t] = words[cur[t]];
+        const uint32_t j = g * 64u + lane;
+        const bool pass = bucket_filter<D>(w, a, rule) && j < n;
+        const unsigned long long mask = __ballot(pass);
+        if (mask) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(q_count, __popcll(mask));
+            base = __shfl(base, 0);
+            if (pass) {
+                const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+                if (pos < kQueue) {
+                    q_items[pos] = static_cast<int>(j);
+                } else {
+                    const int gp = atomicAdd(&p.ovc[l], 1);
+                    p.overflow[gp] = static_cast<int>(j);
+                }
             }
-            if (j >= p.n) continue;
-            if (bound_rejects<D>(v, tau, t2, p.a, p.rule)) continue;
-            double s[D];
-#pragma unroll
-            for (int t = 0; t < D; ++t) s[t] = v[t];
-            sort_values<D>(s);
-            if (!window_pass<D>(s, p.a, t2)) continue;
-            double w;
-            if (exact_score<D>(v, tau, p.rule, p.a, w)) apply_update<D>(p, l, j, w, rows);
         }
+#pragma unroll
+        for (int t = 0; t < D; ++t) cur[t] = nxt[t];
+    }
+    __syncthreads();
+    if (p.timeline && blockIdx.x == 0 && threadIdx.x == 0)
+        p.timeline[3 * p.max_iter + 9 + 3 * l] = static_cast<int64_t>(wall_clock64());
+    const int cnt = min(*q_count, kQueue);
+    for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D>(p, l, q_items[q], tau);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *q_count = 0;
+        if (p.timeline && blockIdx.x == 0)
+            p.timeline[3 * p.max_iter + 10 + 3 * l] = static_cast<int64_t>(wall_clock64());
     }
 }
 
@@ -274,14 +305,29 @@ __device__ double row_residual(const SolveParams& p, int i) {
 // the persistent solve kernel
 // ---------------------------------------------------------------------------
 
-template <int D, bool RL>
-__global__ void __launch_bounds__(kBlock) solve_kernel(SolveParams p, uint64_t limit) {
-    extern __shared__ double lds_r[];
+// Waves per SIMD the compiler must allow: two resident workgroups (8 waves)
+// for small degrees, one for large ones.
+template <int D>
+struct Occ {
+    static constexpr int kWavesPerEU = D <= 9 ? 8 : 4;
+};
+
+template <int D, bool WL>
+__global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(SolveParams p, uint64_t limit) {
+    extern __shared__ uint32_t lds_w[];
+    __shared__ int q_items[kQueue];
+    __shared__ int q_count;
+    if (threadIdx.x == 0) q_count = 0;
     const int tid = threadIdx.x;
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
     const int64_t gsize = static_cast<int64_t>(gridDim.x) * kBlock;
     Ctrl* c = p.ctrl;
-    unsigned epoch = 0;
+    if (p.timeline && blockIdx.x == 0 && tid == 0) p.timeline[0] = static_cast<int64_t>(wall_clock64());
+    BarrierSite site;
+    if (!barrier_setup(c, site, limit)) {
+        if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
+        return;
+    }
 
     // --- init: x_hat, support bitmap, per-row state, max |y|, finiteness
     {
@@ -306,7 +352,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveParams p, uint64_t l
         if (wave_count(bad != 0) && (tid & 63) == 0) atomicExch(&c->err, L0_DEV_NONFINITE_Y);
         if (gtid == 0 && *p.bad_index) atomicExch(&c->err, L0_DEV_BAD_INDEX);
     }
-    if (!grid_sync(c, epoch, limit)) {
+    if (!grid_sync(c, site, limit, p.timeline)) {
         if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
         return;
     }
@@ -318,7 +364,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveParams p, uint64_t l
     const double ymax = __longlong_as_double(static_cast<long long>(
         __hip_atomic_load(&c->maxabs_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
     const double tau = (p.tol_mode == L0_TOL_RELATIVE) ? p.tol * ymax : p.tol;
-    const double t2 = (tau + tau) * (1.0 + 0x1p-40);
+    const double inv_w = 1.0 / bucket_width(tau, ymax);
 
     // --- resume: enter the nonzeros of x_init into the support lists
     if (p.x_init) {
@@ -332,7 +378,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveParams p, uint64_t l
                 p.slots[p.row_off[i] + q] = static_cast<int>(j);
             }
         }
-        if (!grid_sync(c, epoch, limit)) {
+        if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
             return;
         }
@@ -344,12 +390,13 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveParams p, uint64_t l
         for (int64_t i = gtid; i < p.m; i += gsize) {
             const double ri = p.x_init ? row_residual(p, static_cast<int>(i)) : p.y[i];
             p.r[i] = ri;
+            p.rword[i] = row_word(ri, tau, inv_w);
             wnz += wave_count(fabs(ri) > tau);
         }
         const int b = block_sum((tid & 63) == 0 ? wnz : 0);
         if (tid == 0 && b) atomicAdd(&c->nnz, b);
     }
-    if (!grid_sync(c, epoch, limit)) {
+    if (!grid_sync(c, site, limit, p.timeline)) {
         if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
         return;
     }
@@ -364,14 +411,36 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveParams p, uint64_t l
         if (l == p.max_iter) { outcome = L0_MAX_ITER; break; }
 
         // vote on the same residual for every column
-        if (RL) {
-            for (int i = tid; i < p.m; i += kBlock) lds_r[i] = p.r[i];
+        if (WL) {
+            // several loads in flight per thread before the LDS stores
+            int i = tid;
+            for (; i + 3 * kBlock < p.m; i += 4 * kBlock) {
+                const uint32_t a0 = p.rword[i], a1 = p.rword[i + kBlock];
+                const uint32_t a2 = p.rword[i + 2 * kBlock], a3 = p.rword[i + 3 * kBlock];
+                lds_w[i] = a0;
+                lds_w[i + kBlock] = a1;
+                lds_w[i + 2 * kBlock] = a2;
+                lds_w[i + 3 * kBlock] = a3;
+            }
+            for (; i < p.m; i += kBlock) lds_w[i] = p.rword[i];
             __syncthreads();
+            if (p.timeline && blockIdx.x == 0 && tid == 0)
+                p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
         }
-        vote_phase<D, RL>(p, l, tau, t2, lds_r);
-        if (!grid_sync(c, epoch, limit)) {
+        vote_phase<D, WL>(p, l, tau, lds_w, q_items, &q_count);
+        if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
             return;
+        }
+        // columns that overflowed the workgroup queues are scored now, still
+        // on the residual every other column saw
+        const int novf = ld_relaxed(&p.ovc[l]);
+        if (novf > 0) {
+            for (int64_t q = gtid; q < novf; q += gsize) score_exact<D>(p, l, p.overflow[q], tau);
+            if (!grid_sync(c, site, limit, p.timeline)) {
+                if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
+                return;
+            }
         }
         const int tc = ld_relaxed(&p.tcount[l]);
         if (tc == 0) { outcome = L0_STALLED; break; }
@@ -388,13 +457,14 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveParams p, uint64_t l
                 const bool was = fabs(p.r[i]) > tau;
                 const bool now = fabs(rn) > tau;
                 p.r[i] = rn;
+                p.rword[i] = row_word(rn, tau, inv_w);
                 p.aff_flag[i] = 0;
                 wdelta += wave_count(now && !was) - wave_count(was && !now);
             }
             const int b = block_sum((tid & 63) == 0 ? wdelta : 0);
             if (tid == 0 && b) atomicAdd(&c->nnz, b);
         }
-        if (!grid_sync(c, epoch, limit)) {
+        if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
             return;
         }
@@ -515,7 +585,7 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s)
     hipLaunchKernelGGL(zero_ints, dim3(256), dim3(256), 0, s, A.deg, static_cast<int64_t>(A.m));
     hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, A.bad_index, int64_t(1));
     const size_t hist_bytes = static_cast<size_t>(A.m) * sizeof(int);
-    const int lds_hist = hist_bytes <= kLdsRBytes ? 1 : 0;
+    const int lds_hist = hist_bytes <= kLdsWordBytes ? 1 : 0;
     const size_t lds = lds_hist ? hist_bytes : 0;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&repack_kernel<D>),
@@ -534,10 +604,10 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int D, bool RL>
+template <int D, bool WL>
 hipError_t solve_d(const SolveParams& p, hipStream_t s) {
-    const void* fn = reinterpret_cast<const void*>(&solve_kernel<D, RL>);
-    const size_t lds = RL ? static_cast<size_t>(p.m) * sizeof(double) : 0;
+    const void* fn = reinterpret_cast<const void*>(&solve_kernel<D, WL>);
+    const size_t lds = WL ? static_cast<size_t>(p.m) * sizeof(uint32_t) : 0;
     hipError_t e;
     if (lds > 64 * 1024) {
         e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
@@ -556,7 +626,7 @@ hipError_t solve_d(const SolveParams& p, hipStream_t s) {
     hipLaunchKernelGGL(zero_ints, dim3(1), dim3(256), 0, s, reinterpret_cast<int32_t*>(p.ctrl),
                        static_cast<int64_t>(sizeof(Ctrl) / sizeof(int32_t)));
     hipLaunchKernelGGL(zero_ints, dim3(8), dim3(256), 0, s, p.tcount,
-                       static_cast<int64_t>(2 * (p.max_iter + 2)));
+                       static_cast<int64_t>(3 * (p.max_iter + 2)));
     SolveParams q = p;
     uint64_t limit = barrier_limit_ticks();
     void* args[] = {&q, &limit};
@@ -566,7 +636,7 @@ hipError_t solve_d(const SolveParams& p, hipStream_t s) {
 
 template <int D>
 hipError_t solve_dispatch_r(const SolveParams& p, hipStream_t s) {
-    if (static_cast<size_t>(p.m) * sizeof(double) <= kLdsRBytes) return solve_d<D, true>(p, s);
+    if (static_cast<size_t>(p.m) * sizeof(uint32_t) <= kLdsWordBytes) return solve_d<D, true>(p, s);
     return solve_d<D, false>(p, s);
 }
 
