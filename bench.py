@@ -13,8 +13,8 @@ per second.  The roofline object is for the dominant kernel, the persistent
 solve kernel, timed with HIP events on the stream it runs on (torch's current
 stream) over repeated l0_solve calls on the prepared matrix; its algorithmic
 bytes per launch are the per-vote-pass bytes 4nd (streamed column-index
-store) times the number of vote passes, plus 16m per residual pass and the
-x_hat initialisation 8n.  The CPU baseline is the FP64 oracle (one thread)
+store: 2 bytes per index when m <= 36864, else 4) times the number of vote
+passes, plus 16m per residual pass and the x_hat initialisation 8n.  The CPU baseline is the FP64 oracle (one thread)
 on one full decode of the same instance.
 """
 from __future__ import annotations
@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Parallel-ℓ0 solve time & HBM GB/s at n=2^24; batched solves/sec vs plain"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1508_01256_amd/csrc/l0_kernels.hip", "paper_1508_01256_amd/csrc/l0_internal.h"]
+KERNEL_SOURCES = ["paper_1508_01256_amd/csrc/l0_kernels.hip", "paper_1508_01256_amd/csrc/l0_internal.h",
+                  "paper_1508_01256_amd/csrc/l0_filter.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_kernel_n2^24_traffic.json")
 
 
@@ -62,12 +63,18 @@ def passes_of(iters, outcome):
     return iters + (1 if outcome == 1 else 0)
 
 
+def index_bytes(m):
+    """Bytes per stored row index: the library keeps 16-bit rows when the rows'
+    bucket words fit in LDS (4 m <= 144 KiB), else 32-bit rows."""
+    return 2 if 4 * m <= 144 * 1024 else 4
+
+
 def algorithmic_bytes(n, m, d, iters, outcome, tsizes):
     """Bytes the method must move in one solve launch (see module doc)."""
     passes = passes_of(iters, outcome)
     b = 8 * n                      # x_hat = 0
     b += 16 * m                    # r = y (read y, write r)
-    b += passes * 4 * n * d        # column-index stream per vote pass
+    b += passes * index_bytes(m) * n * d  # column-index stream per vote pass
     b += iters * 16 * m            # residual pass: y read + r write (upper bound per row touched)
     b += sum(int(t) for t in tsizes) * (16 + 4 * d)  # x_hat RMW + support-list appends
     return b, passes
@@ -177,15 +184,18 @@ def main():
     sub = []
     for l in range(passes_of(iters, outcome)):
         b = 3 * max_iter + 8 + 3 * l
-        if tlv[b + 2] > 0:
-            sub.append([round((tlv[b + k] - tlv[b + k - 1 if k else b]) / 100.0, 1) for k in range(3)])
+        prev = tlv[2 + 2 * l]  # the barrier that opened this vote
+        if tlv[b + 2] > 0 and prev > 0:
+            sub.append([round((tlv[b] - prev) / 100.0, 1), round((tlv[b + 1] - tlv[b]) / 100.0, 1),
+                        round((tlv[b + 2] - tlv[b + 1]) / 100.0, 1)])
     print(f"[bench] phase timeline (us, between grid barriers): {phases_us}", file=sys.stderr, flush=True)
-    print(f"[bench] vote sub-phases (us since stage/stream/queue): {sub}", file=sys.stderr, flush=True)
+    print(f"[bench] vote sub-phases (us: stage, stream+filter, exact scoring): {sub}", file=sys.stderr,
+          flush=True)
     ts = tsize[:iters].cpu().tolist()
     tr = trace[: iters + 1].cpu().tolist()
     bytes_launch, passes = algorithmic_bytes(n, m, d, iters, outcome, ts)
     achieved = bytes_launch / (solve_avg * 1e-3) / 1e9
-    vote_bytes = 4 * n * d
+    vote_bytes = index_bytes(m) * n * d
     print(f"[bench] solve kernel avg {solve_avg:.3f} ms (min {min(solve_ms):.3f}) over {args.repeats}; "
           f"passes={passes} trace={tr} tsize={ts}; {achieved:.0f} GB/s algorithmic; "
           f"prep {prep_ms:.2f} ms", file=sys.stderr, flush=True)

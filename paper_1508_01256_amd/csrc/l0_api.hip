@@ -20,7 +20,7 @@ namespace l0 {
 MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d) {
     MatrixBuffers b{};
     const int64_t ntiles = (n + kTile - 1) / kTile;
-    b.soa = align256(static_cast<size_t>(ntiles) * d * kTile * sizeof(int32_t));
+    b.soa = align256(static_cast<size_t>(ntiles) * d * kTile * (is_compact(m) ? 2 : 4));
     b.row_off = align256((static_cast<size_t>(m) + 1) * sizeof(int32_t));
     b.deg = align256(static_cast<size_t>(m) * sizeof(int32_t));
     b.flag = 256;
@@ -31,7 +31,7 @@ MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d) {
 SolveBuffers solve_layout(int64_t n, int32_t m, int32_t d, int32_t max_iter) {
     SolveBuffers b{};
     b.ctrl = align256(sizeof(Ctrl));
-    b.counters = align256(3 * (static_cast<size_t>(max_iter) + 2) * sizeof(int32_t));
+    b.counters = align256(4 * (static_cast<size_t>(max_iter) + 2) * sizeof(int32_t));
     b.r = align256(static_cast<size_t>(m) * sizeof(double));
     b.rword = align256(static_cast<size_t>(m) * sizeof(uint32_t));
     b.slot_cnt = b.slot_sorted = b.aff_flag = b.aff_list = align256(static_cast<size_t>(m) * sizeof(int32_t));
@@ -110,7 +110,8 @@ l0::MatrixView carve_matrix(char* base, int64_t n, int32_t m, int32_t d) {
     v.d = d;
     v.ntiles = (n + l0::kTile - 1) / l0::kTile;
     char* p = base;
-    v.soa = reinterpret_cast<int32_t*>(p);       p += b.soa;
+    v.compact = l0::is_compact(m) ? 1 : 0;
+    v.soa = p;                                    p += b.soa;
     v.row_off = reinterpret_cast<int32_t*>(p);   p += b.row_off;
     v.deg = reinterpret_cast<int32_t*>(p);       p += b.deg;
     v.bad_index = reinterpret_cast<int32_t*>(p);
@@ -123,7 +124,8 @@ void carve_solve(l0::SolveParams& q, char* base, int64_t n, int32_t m, int32_t d
     q.ctrl = reinterpret_cast<l0::Ctrl*>(p);            p += b.ctrl;
     q.tcount = reinterpret_cast<int32_t*>(p);
     q.affc = q.tcount + (max_iter + 2);
-    q.ovc = q.affc + (max_iter + 2);                     p += b.counters;
+    q.ovc = q.affc + (max_iter + 2);
+    q.vctr = q.ovc + (max_iter + 2);                     p += b.counters;
     q.r = reinterpret_cast<double*>(p);                  p += b.r;
     q.rword = reinterpret_cast<uint32_t*>(p);            p += b.rword;
     q.slot_cnt = reinterpret_cast<int32_t*>(p);          p += b.slot_cnt;
@@ -143,6 +145,7 @@ l0_status run_solve(const l0::MatrixView& A, const double* y, double alpha, int3
     q.m = A.m;
     q.d = A.d;
     q.ntiles = A.ntiles;
+    q.compact = A.compact;
     q.soa = A.soa;
     q.row_off = A.row_off;
     q.bad_index = A.bad_index;

@@ -15,21 +15,25 @@ constexpr int kTile = 256;          // columns per tile of the repacked index st
 constexpr int kBlock = 1024;        // threads per workgroup of the solve kernel
 constexpr int kWaves = kBlock / 64; // wavefronts per workgroup
 // Row bucket words staged in LDS when 4*m fits under this (gfx950 has 160 KiB
-// per CU; the rest holds the per-workgroup queue and reduction scratch).
+// per CU; the rest holds the per-workgroup queue and reduction scratch).  Such
+// "compact" problems (m <= 36864) also store row indices as 16 bits.
 constexpr size_t kLdsWordBytes = 144 * 1024;
+inline bool is_compact(int32_t m) { return static_cast<size_t>(m) * 4 <= kLdsWordBytes; }
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Device-resident prepared matrix (layout of the repacked column-index store):
 //   soa[(tile*d + t)*kTile + c] = row of column tile*kTile + c, t-th neighbour
-// (columns past n hold row 0 and are never scored); row_off[i] .. row_off[i+1]
-// is row i's capacity region in the per-row support lists (its degree in A).
+// as uint16 when compact, else int32 (columns past n hold row 0 and are never
+// scored); row_off[i] .. row_off[i+1] is row i's capacity region in the
+// per-row support lists (its degree in A).
 struct MatrixView {
     int64_t n;
     int32_t m;
     int32_t d;
     int64_t ntiles;
-    int32_t* soa;
+    int32_t compact;    // is_compact(m): 16-bit rows, bucket words in LDS
+    void* soa;
     int32_t* row_off;   // int32[m+1]
     int32_t* deg;       // int32[m] scratch for the degree histogram
     int32_t* bad_index; // int32[1]: nonzero when a row index was out of range
@@ -71,7 +75,8 @@ struct SolveParams {
     int32_t m;
     int32_t d;
     int64_t ntiles;
-    const int32_t* soa;
+    int32_t compact;
+    const void* soa;
     const int32_t* row_off;
     const int32_t* bad_index;
     const double* y;
@@ -93,6 +98,7 @@ struct SolveParams {
     int32_t* tcount;     // int32[max_iter+2]
     int32_t* affc;       // int32[max_iter+2]
     int32_t* ovc;        // int32[max_iter+2]: columns in the overflow queue per iteration
+    int32_t* vctr;       // int32[max_iter+2]: chunks claimed by the vote of each iteration
     double* r;
     uint32_t* rword;     // uint32[m]: bucket word of each residual entry
     int32_t* slot_cnt;

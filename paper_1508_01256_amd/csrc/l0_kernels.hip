@@ -153,6 +153,14 @@ __device__ __forceinline__ int64_t soa_index(int64_t j, int t, int d) {
     return ((j / kTile) * d + t) * kTile + (j % kTile);
 }
 
+// Row index of column j's t-th neighbour in the repacked store (16-bit
+// entries for compact problems, 32-bit otherwise).
+template <bool COMPACT>
+__device__ __forceinline__ int soa_row(const void* soa, int64_t j, int t, int d) {
+    if constexpr (COMPACT) return static_cast<const uint16_t*>(soa)[soa_index(j, t, d)];
+    else return static_cast<const int32_t*>(soa)[soa_index(j, t, d)];
+}
+
 __device__ void write_result(const SolveParams& p, int iters, int outcome, int nnz, int support,
                              long long updates) {
     p.res->iters = iters;
@@ -191,77 +199,99 @@ __device__ void apply_update(const SolveParams& p, int l, int64_t j, double w, c
 
 // Exact scoring of one column that passed the bucket filter: its rows come
 // from the repacked index store, its values from the FP64 residual.
-template <int D>
+template <int D, bool COMPACT>
 __device__ void score_exact(const SolveParams& p, int l, int64_t j, double tau) {
     int rows[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) rows[t] = soa_row<COMPACT>(p.soa, j, t, D);
     double v[D];
 #pragma unroll
-    for (int t = 0; t < D; ++t) {
-        rows[t] = p.soa[soa_index(j, t, D)];
-        v[t] = p.r[rows[t]];
-    }
+    for (int t = 0; t < D; ++t) v[t] = p.r[rows[t]];
     double w;
     if (exact_score<D>(v, tau, p.rule, p.a, w)) apply_update<D>(p, l, j, w, rows);
 }
 
 constexpr int kQueue = 2048;  // per-workgroup queue of columns passing the filter
 
-// Rows of the 64 columns of chunk g (columns 64g .. 64g+63), one per lane:
-// the chunk is a quarter of a tile, so each neighbour plane is one coalesced
-// 256-byte load.  Offsets fit 32 bits (n*d < 2^31), which keeps one base
-// register pair for the whole stream.
-template <int D>
-__device__ __forceinline__ void load_chunk(const int32_t* __restrict__ soa, uint32_t g, uint32_t lane,
-                                           int (&rows)[D]) {
-    const uint32_t base = (g >> 2) * (D * kTile) + (g & 3u) * 64u + lane;
+// A chunk is the unit a wave streams: 128 columns (two 16-bit rows per lane
+// and plane) for compact problems, else 64 columns (one 32-bit row per lane).
+// Each neighbour plane of a chunk is one coalesced 256-byte load.
+template <bool COMPACT>
+struct Chunk {
+    static constexpr uint32_t kCols = COMPACT ? 128 : 64;
+    static constexpr uint32_t kPerTile = kTile / kCols;
+};
+
+template <int D, bool COMPACT>
+__device__ __forceinline__ void load_chunk(const void* soa, uint32_t g, uint32_t lane, uint32_t (&rows)[D]) {
+    const uint32_t* __restrict__ s32 = static_cast<const uint32_t*>(soa);
+    constexpr uint32_t plane = COMPACT ? kTile / 2 : kTile;  // 32-bit words per plane of a tile
+    constexpr uint32_t per = Chunk<COMPACT>::kPerTile;
+    const uint32_t base = (g / per) * (D * plane) + (g % per) * 64u + lane;
 #pragma unroll
-    for (int t = 0; t < D; ++t) rows[t] = __builtin_nontemporal_load(soa + (base + t * kTile));
+    for (int t = 0; t < D; ++t) rows[t] = __builtin_nontemporal_load(s32 + (base + t * plane));
 }
 
-// Vote phase: waves stride over 64-column chunks, prefetching the next
-// chunk's row indices while the current chunk gathers its rows' bucket words
-// (from LDS when staged) and runs the bucket filter.  Columns passing it are
-// compacted per wave into an LDS queue (a global queue takes any overflow)
-// and scored exactly once the chunks are done.
-template <int D, bool WL>
+// Filter the columns of one chunk; passing columns are compacted per wave into
+// the workgroup's LDS queue, or the global overflow queue once it is full.
+template <int D>
+__device__ __forceinline__ void filter_and_queue(const SolveParams& p, int l, const uint32_t (&w)[D],
+                                                 uint32_t j, uint32_t n, uint32_t lane, int* q_items,
+                                                 int* q_count) {
+    const bool pass = bucket_filter<D>(w, p.a, p.rule) && j < n;
+    const unsigned long long mask = __ballot(pass);
+    if (mask) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(q_count, __popcll(mask));
+        base = __shfl(base, 0);
+        if (pass) {
+            const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+            if (pos < kQueue) {
+                q_items[pos] = static_cast<int>(j);
+            } else {
+                const int gp = atomicAdd(&p.ovc[l], 1);
+                p.overflow[gp] = static_cast<int>(j);
+            }
+        }
+    }
+}
+
+// Vote phase.  Waves stride over chunks, prefetching the next chunk's row
+// indices while the current chunk gathers its rows' bucket words and runs the
+// bucket filter.  Columns passing it are scored exactly once the chunks are
+// done, on the same residual.
+template <int D, bool COMPACT>
 __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32_t* lds_w,
                            int* q_items, int* q_count) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t nchunks = static_cast<uint32_t>(p.ntiles * (kTile / 64));
-    const uint32_t stride = gridDim.x * kWaves;
+    constexpr uint32_t kCols = Chunk<COMPACT>::kCols;
+    const uint32_t nchunks = static_cast<uint32_t>(p.ntiles) * Chunk<COMPACT>::kPerTile;
     const uint32_t n = static_cast<uint32_t>(p.n);
-    const int a = p.a, rule = p.rule;
-    const int32_t* __restrict__ soa = p.soa;
-    const uint32_t* __restrict__ words = WL ? lds_w : p.rword;
+    const uint32_t* __restrict__ words = COMPACT ? lds_w : p.rword;
+    const uint32_t stride = gridDim.x * kWaves;
     uint32_t g = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    int cur[D];
+    uint32_t cur[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) cur[t] = 0;
-    if (g < nchunks) load_chunk<D>(soa, g, lane, cur);
+    if (g < nchunks) load_chunk<D, COMPACT>(p.soa, g, lane, cur);
     for (; g < nchunks; g += stride) {
-        int nxt[D];
+        uint32_t nxt[D];
 #pragma unroll
         for (int t = 0; t < D; ++t) nxt[t] = 0;
-        if (g + stride < nchunks) load_chunk<D>(soa, g + stride, lane, nxt);
-        uint32_t w[D];
+        if (g + stride < nchunks) load_chunk<D, COMPACT>(p.soa, g + stride, lane, nxt);
+        if constexpr (COMPACT) {
 #pragma unroll
-        for (int t = 0; t < D; ++t) w[t] = words[cur[t]];
-        const uint32_t j = g * 64u + lane;
-        const bool pass = bucket_filter<D>(w, a, rule) && j < n;
-        const unsigned long long mask = __ballot(pass);
-        if (mask) {
-            int base = 0;
-            if (lane == 0) base = atomicAdd(q_count, __popcll(mask));
-            base = __shfl(base, 0);
-            if (pass) {
-                const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-                if (pos < kQueue) {
-                    q_items[pos] = static_cast<int>(j);
-                } else {
-                    const int gp = atomicAdd(&p.ovc[l], 1);
-                    p.overflow[gp] = static_cast<int>(j);
-                }
+            for (int h = 0; h < 2; ++h) {
+                uint32_t w[D];
+#pragma unroll
+                for (int t = 0; t < D; ++t) w[t] = words[h ? (cur[t] >> 16) : (cur[t] & 0xFFFFu)];
+                filter_and_queue<D>(p, l, w, g * kCols + 2 * lane + h, n, lane, q_items, q_count);
             }
+        } else {
+            uint32_t w[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) w[t] = words[cur[t]];
+            filter_and_queue<D>(p, l, w, g * kCols + lane, n, lane, q_items, q_count);
         }
 #pragma unroll
         for (int t = 0; t < D; ++t) cur[t] = nxt[t];
@@ -270,7 +300,7 @@ __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32
     if (p.timeline && blockIdx.x == 0 && threadIdx.x == 0)
         p.timeline[3 * p.max_iter + 9 + 3 * l] = static_cast<int64_t>(wall_clock64());
     const int cnt = min(*q_count, kQueue);
-    for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D>(p, l, q_items[q], tau);
+    for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D, COMPACT>(p, l, q_items[q], tau);
     __syncthreads();
     if (threadIdx.x == 0) {
         *q_count = 0;
@@ -312,7 +342,7 @@ struct Occ {
     static constexpr int kWavesPerEU = D <= 9 ? 8 : 4;
 };
 
-template <int D, bool WL>
+template <int D, bool COMPACT>
 __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(SolveParams p, uint64_t limit) {
     extern __shared__ uint32_t lds_w[];
     __shared__ int q_items[kQueue];
@@ -373,7 +403,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             atomicOr(&p.member[j >> 5], 1u << (j & 31));
             atomicAdd(&c->support, 1);
             for (int t = 0; t < D; ++t) {
-                const int i = p.soa[soa_index(j, t, D)];
+                const int i = soa_row<COMPACT>(p.soa, j, t, D);
                 const int q = atomicAdd(&p.slot_cnt[i], 1);
                 p.slots[p.row_off[i] + q] = static_cast<int>(j);
             }
@@ -411,7 +441,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         if (l == p.max_iter) { outcome = L0_MAX_ITER; break; }
 
         // vote on the same residual for every column
-        if (WL) {
+        if (COMPACT) {
             // several loads in flight per thread before the LDS stores
             int i = tid;
             for (; i + 3 * kBlock < p.m; i += 4 * kBlock) {
@@ -427,7 +457,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             if (p.timeline && blockIdx.x == 0 && tid == 0)
                 p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
         }
-        vote_phase<D, WL>(p, l, tau, lds_w, q_items, &q_count);
+        vote_phase<D, COMPACT>(p, l, tau, lds_w, q_items, &q_count);
         if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
             return;
@@ -436,7 +466,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         // on the residual every other column saw
         const int novf = ld_relaxed(&p.ovc[l]);
         if (novf > 0) {
-            for (int64_t q = gtid; q < novf; q += gsize) score_exact<D>(p, l, p.overflow[q], tau);
+            for (int64_t q = gtid; q < novf; q += gsize) score_exact<D, COMPACT>(p, l, p.overflow[q], tau);
             if (!grid_sync(c, site, limit, p.timeline)) {
                 if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
                 return;
@@ -489,37 +519,54 @@ __global__ void zero_ints(int32_t* p, int64_t count) {
         p[i] = 0;
 }
 
-// Repack col_idx (column-major rows) into the tiled neighbour planes, check
-// every row index, and count row degrees (LDS histogram when m fits).
-template <int D>
+// Repack col_idx (each column's d rows contiguous) into the tiled neighbour
+// planes, check every row index, and count row degrees (LDS histogram when m
+// fits, else global atomics).  Each wave takes groups of 64 columns: it reads
+// the group's 64*D contiguous indices with coalesced loads into an LDS
+// staging area and writes each neighbour plane's 64 entries contiguously.
+constexpr int kRepackWaves = 16;
+template <int D, typename IT>
 __global__ void __launch_bounds__(1024) repack_kernel(const int32_t* col_idx, MatrixView A, int lds_hist) {
-    extern __shared__ int hist[];
-    const int64_t gtid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t gsize = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    if (lds_hist) {
+    extern __shared__ int sh[];
+    int* hist = sh;
+    int* stage = sh + (lds_hist ? A.m : 0) + (threadIdx.x >> 6) * (64 * D);
+    const int lane = threadIdx.x & 63;
+    if (lds_hist)
         for (int i = threadIdx.x; i < A.m; i += blockDim.x) hist[i] = 0;
-        __syncthreads();
-    }
-    const int64_t total = A.ntiles * D * kTile;
+    __syncthreads();
+    const int64_t nd = A.n * D;
+    const int64_t ngroups = A.ntiles * (kTile / 64);
     int bad = 0;
-    for (int64_t o = gtid; o < total; o += gsize) {
-        const int64_t tile = o / (D * kTile);
-        const int rem = static_cast<int>(o - tile * (D * kTile));
-        const int t = rem / kTile;
-        const int64_t j = tile * kTile + (rem - t * kTile);
-        int row = 0;
-        if (j < A.n) {
-            row = col_idx[j * D + t];
-            if (row < 0 || row >= A.m) {
-                bad = 1;
-                row = 0;
-            } else if (lds_hist) {
-                atomicAdd(&hist[row], 1);
-            } else {
-                atomicAdd(&A.deg[row], 1);
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * kRepackWaves + (threadIdx.x >> 6); g < ngroups;
+         g += static_cast<int64_t>(gridDim.x) * kRepackWaves) {
+        const int64_t e0 = g * 64 * D;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int64_t e = e0 + k * 64 + lane;
+            int row = 0;
+            if (e < nd) {
+                row = __builtin_nontemporal_load(&col_idx[e]);
+                if (row < 0 || row >= A.m) {
+                    bad = 1;
+                    row = 0;
+                } else if (lds_hist) {
+                    atomicAdd(&hist[row], 1);
+                } else {
+                    atomicAdd(&A.deg[row], 1);
+                }
             }
+            stage[k * 64 + lane] = row;
         }
-        A.soa[o] = row;
+        // the wave's LDS stores complete (lgkmcnt(0)) before any lane reads
+        // another lane's entries; the wave barrier keeps the compiler from
+        // moving the reads above
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        __builtin_amdgcn_wave_barrier();
+        const int64_t tile = g / (kTile / 64);
+        const int c = static_cast<int>(g % (kTile / 64)) * 64 + lane;
+#pragma unroll
+        for (int t = 0; t < D; ++t)
+            static_cast<IT*>(A.soa)[(tile * D + t) * kTile + c] = static_cast<IT>(stage[lane * D + t]);
     }
     if (bad) atomicExch(A.bad_index, 1);
     if (lds_hist) {
@@ -585,29 +632,34 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s)
     hipLaunchKernelGGL(zero_ints, dim3(256), dim3(256), 0, s, A.deg, static_cast<int64_t>(A.m));
     hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, A.bad_index, int64_t(1));
     const size_t hist_bytes = static_cast<size_t>(A.m) * sizeof(int);
-    const int lds_hist = hist_bytes <= kLdsWordBytes ? 1 : 0;
-    const size_t lds = lds_hist ? hist_bytes : 0;
+    const size_t stage_bytes = static_cast<size_t>(kRepackWaves) * 64 * D * sizeof(int);
+    const int lds_hist = hist_bytes + stage_bytes <= kLdsWordBytes ? 1 : 0;
+    const size_t lds = (lds_hist ? hist_bytes : 0) + stage_bytes;
+    const void* fn = A.compact ? reinterpret_cast<const void*>(&repack_kernel<D, uint16_t>)
+                               : reinterpret_cast<const void*>(&repack_kernel<D, int32_t>);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&repack_kernel<D>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           static_cast<int>(lds));
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
-    const int64_t total = A.ntiles * D * kTile;
-    int64_t blocks = (total + 1023) / 1024;
-    const int64_t cap = static_cast<int64_t>(cus > 0 ? cus : 256) * (lds_hist ? 1 : 8);
+    const int64_t groups = A.ntiles * (kTile / 64);
+    int64_t blocks = (groups + kRepackWaves - 1) / kRepackWaves;
+    const int64_t cap = static_cast<int64_t>(cus > 0 ? cus : 256) * (lds_hist ? 1 : 2);
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(repack_kernel<D>, dim3(static_cast<unsigned>(blocks)), dim3(1024), lds, s, col_idx, A,
-                       lds_hist);
+    if (A.compact)
+        hipLaunchKernelGGL((repack_kernel<D, uint16_t>), dim3(static_cast<unsigned>(blocks)), dim3(1024), lds, s,
+                           col_idx, A, lds_hist);
+    else
+        hipLaunchKernelGGL((repack_kernel<D, int32_t>), dim3(static_cast<unsigned>(blocks)), dim3(1024), lds, s,
+                           col_idx, A, lds_hist);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, A);
     return hipGetLastError();
 }
 
-template <int D, bool WL>
+template <int D, bool COMPACT>
 hipError_t solve_d(const SolveParams& p, hipStream_t s) {
-    const void* fn = reinterpret_cast<const void*>(&solve_kernel<D, WL>);
-    const size_t lds = WL ? static_cast<size_t>(p.m) * sizeof(uint32_t) : 0;
+    const void* fn = reinterpret_cast<const void*>(&solve_kernel<D, COMPACT>);
+    const size_t lds = COMPACT ? static_cast<size_t>(p.m) * sizeof(uint32_t) : 0;
     hipError_t e;
     if (lds > 64 * 1024) {
         e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
@@ -626,7 +678,7 @@ hipError_t solve_d(const SolveParams& p, hipStream_t s) {
     hipLaunchKernelGGL(zero_ints, dim3(1), dim3(256), 0, s, reinterpret_cast<int32_t*>(p.ctrl),
                        static_cast<int64_t>(sizeof(Ctrl) / sizeof(int32_t)));
     hipLaunchKernelGGL(zero_ints, dim3(8), dim3(256), 0, s, p.tcount,
-                       static_cast<int64_t>(3 * (p.max_iter + 2)));
+                       static_cast<int64_t>(4 * (p.max_iter + 2)));
     SolveParams q = p;
     uint64_t limit = barrier_limit_ticks();
     void* args[] = {&q, &limit};
@@ -636,7 +688,7 @@ hipError_t solve_d(const SolveParams& p, hipStream_t s) {
 
 template <int D>
 hipError_t solve_dispatch_r(const SolveParams& p, hipStream_t s) {
-    if (static_cast<size_t>(p.m) * sizeof(uint32_t) <= kLdsWordBytes) return solve_d<D, true>(p, s);
+    if (p.compact) return solve_d<D, true>(p, s);
     return solve_d<D, false>(p, s);
 }
 

@@ -55,7 +55,10 @@ def test_small_workload_mode_rule(seed):
 @pytest.mark.parametrize("n,m,d,k", [
     (100003, 10007, 7, 700),    # many tiles, ragged tail, r in LDS
     (100003, 10007, 7, 2500),   # stalls (dense for alpha = 4)
-    (262144, 26215, 7, 2621),   # m too large for LDS: r gathered from L2
+    (262144, 26215, 7, 2621),   # 16-bit rows, bucket words in LDS
+    (400000, 40000, 7, 3000),   # m too large for LDS: 32-bit rows, words from L2
+    (300000, 36864, 9, 2000),   # largest m with words in LDS
+    (300000, 36865, 5, 2000),   # smallest m without
     (50000, 5000, 5, 400),
     (50000, 5000, 9, 300),
     (30000, 3000, 3, 150),
