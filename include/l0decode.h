@@ -183,6 +183,70 @@ l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter,
                    double* x_out, const l0_opts* opts, l0_result* res_out, void* workspace,
                    size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Batched decoding: many independent instances (each its own A, y, sizes,
+ * alpha, max_iter, tol) of Algorithm 2, as in the phase-transition sweeps of
+ * the paper's experiments (Section 5).  One persistent launch per range of
+ * column degrees present ([2,4], [5,9], [10,14], [15,20]); a workgroup
+ * decodes one instance at a time and takes the next (largest n*d first) from
+ * a device counter.  Each instance's result is
+ * bitwise the one l0_decode_ex gives it alone.  Instances must not share
+ * x_out buffers.
+ */
+typedef struct {
+    const int32_t* col_idx; /* device int32[n*d], as l0_decode */
+    int64_t n;
+    int32_t m;
+    int32_t d;
+    const double* y;        /* device double[m] */
+    double alpha;           /* in (1, d] */
+    int32_t max_iter;       /* >= 0 */
+    int32_t reserved;       /* must be 0 */
+    double tol;             /* >= 0, finite */
+    double* x_out;          /* device double[n], receives x_hat */
+} l0_problem;
+
+/* Launch schedule of l0_decode_batched; zero fields mean "default". */
+typedef struct {
+    int32_t rule;          /* l0_rule for every instance */
+    int32_t tol_mode;      /* l0_tol_mode for every instance */
+    int32_t block_threads; /* 256 or 512 threads per workgroup (0: 256) */
+    int32_t words_cap;     /* bucket words in LDS when m <= words_cap (0: 8192; else 64..32768) */
+    int64_t* timing;       /* optional device int64[8*count]; record i (in ticks of the
+                              device's constant 100 MHz clock): [0] start, [1] end,
+                              [2] setup, [3] vote, [4] scoring and updates, [5] residual
+                              (totals over iterations), [6] workgroup, [7] 0 */
+} l0_batch_opts;
+
+/*
+ * Bytes of workspace l0_decode_batched needs for `probs[0..count)` (a host
+ * array) under `opts` (NULL: enough for every schedule l0_batch_autotune
+ * tries).  0 on invalid arguments.  Queries the current device's occupancy.
+ */
+size_t l0_batch_workspace_bytes(const l0_problem* probs, int32_t count, const l0_batch_opts* opts);
+
+/*
+ * Decode probs[0..count) (host array of device pointers) on `stream`.  results: device l0_result[count] (instance i's at i).
+ * Workspace: device memory of at least l0_batch_workspace_bytes, 256-byte
+ * aligned, caller-owned.  Every instance is validated on the host first
+ * (L0_ERR_ARG names no instance; check them individually to find it).
+ * Row-index and non-finite-y problems are per-instance outcomes.
+ */
+l0_status l0_decode_batched(const l0_problem* probs, int32_t count, const l0_batch_opts* opts,
+                            l0_result* results, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Pick the schedule for a batch: runs each candidate (workgroup size, LDS
+ * word capacity) on a sample of at most 256 of the instances, times it on
+ * `stream` (this call synchronises the stream), and writes the fastest into
+ * *opts (rule and tol_mode are kept).  The sample's x_out buffers and
+ * results[0..256) are overwritten: decode the batch afterwards.
+ * Workspace as l0_batch_workspace_bytes(probs, count, NULL).  L0_ERR_WORKSPACE
+ * if no candidate fits ws_bytes.
+ */
+l0_status l0_batch_autotune(const l0_problem* probs, int32_t count, l0_batch_opts* opts,
+                            l0_result* results, void* workspace, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

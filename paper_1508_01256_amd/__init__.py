@@ -35,7 +35,8 @@ L0_TOL_RELATIVE, L0_TOL_ABSOLUTE = 0, 1
 
 #: every entry point declared in include/l0decode.h
 EXPORTED = ("l0_version", "l0_status_string", "l0_decode", "l0_workspace_bytes", "l0_decode_ex",
-            "l0_matrix_create", "l0_matrix_destroy", "l0_solve_workspace_bytes", "l0_solve")
+            "l0_matrix_create", "l0_matrix_destroy", "l0_solve_workspace_bytes", "l0_solve",
+            "l0_batch_workspace_bytes", "l0_decode_batched", "l0_batch_autotune")
 
 
 class LibraryMissing(RuntimeError):
@@ -53,6 +54,19 @@ class l0_opts(ctypes.Structure):
                 ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
                 ("x_init", ctypes.c_void_p), ("trace", ctypes.c_void_p),
                 ("tsize", ctypes.c_void_p), ("timeline", ctypes.c_void_p)]
+
+
+class l0_problem(ctypes.Structure):
+    _fields_ = [("col_idx", ctypes.c_void_p), ("n", ctypes.c_int64), ("m", ctypes.c_int32),
+                ("d", ctypes.c_int32), ("y", ctypes.c_void_p), ("alpha", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("x_out", ctypes.c_void_p)]
+
+
+class l0_batch_opts(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("words_cap", ctypes.c_int32),
+                ("timing", ctypes.c_void_p)]
 
 
 _lib = None
@@ -77,7 +91,12 @@ def lib():
         L.l0_matrix_destroy.argtypes = [P]
         L.l0_solve_workspace_bytes.argtypes, L.l0_solve_workspace_bytes.restype = [P, I32], SZ
         L.l0_solve.argtypes = [P, P, F64, I32, F64, P, P, P, P, SZ, P]
-        for f in ("l0_decode", "l0_decode_ex", "l0_matrix_create", "l0_matrix_destroy", "l0_solve"):
+        L.l0_batch_workspace_bytes.argtypes = [P, I32, P]
+        L.l0_batch_workspace_bytes.restype = SZ
+        L.l0_decode_batched.argtypes = [P, I32, P, P, P, SZ, P]
+        L.l0_batch_autotune.argtypes = [P, I32, P, P, P, SZ, P]
+        for f in ("l0_decode", "l0_decode_ex", "l0_matrix_create", "l0_matrix_destroy", "l0_solve",
+                  "l0_decode_batched", "l0_batch_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -151,6 +170,34 @@ def l0_solve(h, y, alpha, max_iter, tol, x_out, opts, res_out, workspace) -> int
                           _ptr(workspace), 0 if workspace is None else workspace.numel(), _stream())
 
 
+def problem_table(problems):
+    """A ctypes l0_problem array from dicts with keys col_idx, n, m, d, y,
+    alpha, max_iter, tol and x_out (tensors for the buffers)."""
+    arr = (l0_problem * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = l0_problem(p["col_idx"].data_ptr(), p["n"], p["m"], p["d"], p["y"].data_ptr(),
+                            float(p["alpha"]), p["max_iter"], 0, float(p["tol"]),
+                            p["x_out"].data_ptr())
+    return arr
+
+
+def l0_batch_workspace_bytes(table, opts=None) -> int:
+    return lib().l0_batch_workspace_bytes(table, len(table),
+                                          None if opts is None else ctypes.byref(opts))
+
+
+def l0_decode_batched(table, opts, results, workspace) -> int:
+    return lib().l0_decode_batched(table, len(table), None if opts is None else ctypes.byref(opts),
+                                   _ptr(results), _ptr(workspace),
+                                   0 if workspace is None else workspace.numel(), _stream())
+
+
+def l0_batch_autotune(table, opts, results, workspace) -> int:
+    return lib().l0_batch_autotune(table, len(table), ctypes.byref(opts), _ptr(results),
+                                   _ptr(workspace), 0 if workspace is None else workspace.numel(),
+                                   _stream())
+
+
 # ---------------------------------------------------------------------------
 # conveniences
 # ---------------------------------------------------------------------------
@@ -187,6 +234,48 @@ def decode(col_idx, y, n, m, d, alpha=None, *, max_iter=100, tol=1e-10, rule=L0_
     _check(l0_decode_ex(col_idx, n, m, d, y, alpha, max_iter, tol, x, o, res, ws), "l0_decode_ex")
     torch.cuda.current_stream().synchronize()
     return _result_dict(res, trace, tsize, x)
+
+
+def new_results(count, device="cuda"):
+    """A device buffer for `count` l0_result records (as int64[count, 3])."""
+    return torch.zeros((count, 3), dtype=torch.int64, device=device)
+
+
+def results_list(results):
+    """Host dicts (iters, outcome, final_nnz, support_size, updates) of a
+    batched results buffer."""
+    r = results.cpu()
+    i32 = r[:, :2].contiguous().view(torch.int32).reshape(-1, 4).tolist()
+    upd = r[:, 2].tolist()
+    return [dict(iters=a, outcome=b, final_nnz=c, support_size=e, updates=u)
+            for (a, b, c, e), u in zip(i32, upd)]
+
+
+def decode_batched(problems, *, rule=L0_RULE_L0DEC, tol_mode=L0_TOL_RELATIVE, block_threads=0,
+                   words_cap=0, autotune=False):
+    """Decode many instances with l0_decode_batched.  `problems` are dicts as
+    for problem_table; missing x_out buffers are allocated, alpha defaults to
+    ceil(d/2), max_iter to 100, tol to 1e-10.  Returns (x list, result dicts)."""
+    full = []
+    for p in problems:
+        q = dict(p)
+        q.setdefault("alpha", float(max(math.ceil(q["d"] / 2), 2)))
+        q.setdefault("max_iter", 100)
+        q.setdefault("tol", 1e-10)
+        if q.get("x_out") is None:
+            q["x_out"] = torch.empty(q["n"], dtype=torch.float64, device=q["y"].device)
+        full.append(q)
+    table = problem_table(full)
+    opts = l0_batch_opts(rule, tol_mode, block_threads, words_cap)
+    dev = full[0]["y"].device
+    results = new_results(len(full), dev)
+    ws = torch.empty(l0_batch_workspace_bytes(table, None if autotune else opts), dtype=torch.uint8,
+                     device=dev)
+    if autotune:
+        _check(l0_batch_autotune(table, opts, results, ws), "l0_batch_autotune")
+    _check(l0_decode_batched(table, opts, results, ws), "l0_decode_batched")
+    torch.cuda.current_stream().synchronize()
+    return [q["x_out"] for q in full], results_list(results)
 
 
 class Matrix:

@@ -311,3 +311,288 @@ l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched decoding
+// ---------------------------------------------------------------------------
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "l0_batch.h"
+
+namespace {
+
+// Instances of one degree range (l0::kBatchRanges): they run in one
+// persistent launch of that range's kernel.
+struct Group {
+    int range = 0;
+    int d = 0;  // largest degree in the group
+    int32_t start = 0, count = 0;  // range of the processing order
+    int64_t max_n = 0, max_nd = 0;
+    int32_t max_m = 0;
+    int words_cap = 0;
+    size_t lds = 0;
+    int grid = 0;
+    l0::BatchLayout lay{};
+};
+
+struct BatchPlan {
+    int block_threads = 256;
+    int words_cap = 8192;
+    std::vector<int32_t> order;  // by degree, then largest work (n*d) first
+    std::vector<Group> groups;
+    size_t table = 0, order_bytes = 0, counters = 0, scratch = 0, total = 0;
+};
+
+constexpr size_t kLdsLimit = 160 * 1024 - 1024;  // dynamic LDS bound (static use is < 1 KiB)
+
+bool batch_opts_ok(const l0_batch_opts* o) {
+    if (!o) return true;
+    if (o->rule != L0_RULE_L0DEC && o->rule != L0_RULE_MODE) return false;
+    if (o->tol_mode != L0_TOL_RELATIVE && o->tol_mode != L0_TOL_ABSOLUTE) return false;
+    if (o->block_threads != 0 && o->block_threads != 256 && o->block_threads != 512) return false;
+    return o->words_cap == 0 || (o->words_cap >= 64 && o->words_cap <= 32768);
+}
+
+// Validate every instance (sizes and scalars always; buffers when asked),
+// order them and group them by degree.
+bool problems_ok(const l0_problem* probs, int32_t count, BatchPlan& pl, bool buffers) {
+    if (!probs || count < 1) return false;
+    for (int32_t i = 0; i < count; ++i) {
+        const l0_problem& P = probs[i];
+        if (!sizes_ok(P.n, P.m, P.d) || !solve_args_ok(P.alpha, P.d, P.max_iter, P.tol) || P.reserved != 0)
+            return false;
+        if (buffers) {
+            if (!buffer_ok(P.col_idx, static_cast<size_t>(P.n) * P.d * sizeof(int32_t))) return false;
+            if (!buffer_ok(P.y, static_cast<size_t>(P.m) * sizeof(double))) return false;
+            if (!buffer_ok(P.x_out, static_cast<size_t>(P.n) * sizeof(double))) return false;
+        }
+    }
+    pl.order.resize(count);
+    std::iota(pl.order.begin(), pl.order.end(), 0);
+    std::stable_sort(pl.order.begin(), pl.order.end(), [&](int32_t a, int32_t b) {
+        const int ra = l0::batch_range_of(probs[a].d), rb = l0::batch_range_of(probs[b].d);
+        if (ra != rb) return ra < rb;
+        return probs[a].n * probs[a].d > probs[b].n * probs[b].d;
+    });
+    pl.groups.clear();
+    for (int32_t q = 0; q < count; ++q) {
+        const l0_problem& P = probs[pl.order[q]];
+        const int range = l0::batch_range_of(P.d);
+        if (pl.groups.empty() || pl.groups.back().range != range) {
+            Group g;
+            g.range = range;
+            g.start = q;
+            pl.groups.push_back(g);
+        }
+        Group& g = pl.groups.back();
+        ++g.count;
+        g.d = std::max(g.d, static_cast<int>(P.d));
+        g.max_n = std::max(g.max_n, P.n);
+        g.max_m = std::max(g.max_m, P.m);
+        g.max_nd = std::max(g.max_nd, P.n * static_cast<int64_t>(P.d));
+    }
+    return true;
+}
+
+l0::BatchLayout batch_layout(int64_t N, int32_t M, int64_t ND) {
+    using l0::align256;
+    l0::BatchLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o += align256(bytes); return at; };
+    L.r = take(static_cast<size_t>(M) * 8);
+    L.rword = take(static_cast<size_t>(M) * 4);
+    L.member = take(static_cast<size_t>((N + 31) / 32) * 4);
+    L.slot_cnt = take(static_cast<size_t>(M) * 4);
+    L.slot_sorted = take(static_cast<size_t>(M) * 4);
+    L.aff_flag = take(static_cast<size_t>(M) * 4);
+    L.aff_list = take(static_cast<size_t>(M) * 4);
+    L.long_rows = take(static_cast<size_t>(M) * 4);
+    L.row_off = take((static_cast<size_t>(M) + 1) * 4);
+    L.slots = take(static_cast<size_t>(ND) * 4);
+    L.overflow = take(static_cast<size_t>(N) * 4);
+    L.stride = o;
+    return L;
+}
+
+// Resident workgroups, LDS and byte layout of every degree group for one
+// schedule (block size, bucket-word capacity); false if infeasible.  Groups
+// run one after another on the stream, so they share the scratch region.
+bool plan_batch(int32_t count, int block_threads, int words_cap, BatchPlan& pl) {
+    pl.block_threads = block_threads;
+    pl.words_cap = words_cap;
+    const int cus = l0::device_cus();
+    size_t scratch = 0;
+    for (Group& g : pl.groups) {
+        // no more LDS words than the group's largest m needs
+        const int64_t need = (static_cast<int64_t>(g.max_m) + 63) / 64 * 64;
+        g.words_cap = static_cast<int>(std::min<int64_t>(words_cap, need));
+        g.lds = l0::batch_lds_bytes(block_threads, g.words_cap, g.d);
+        if (g.lds > kLdsLimit) return false;
+        const void* fn = l0::batch_kernel_fn(block_threads, g.range);
+        if (!fn) return false;
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g.lds)) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block_threads, g.lds) != hipSuccess ||
+            per_cu < 1) {
+            (void)hipGetLastError();
+            return false;
+        }
+        g.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(per_cu) * (cus > 0 ? cus : 1), g.count));
+        g.lay = batch_layout(g.max_n, g.max_m, g.max_nd);
+        scratch = std::max(scratch, static_cast<size_t>(g.grid) * g.lay.stride);
+    }
+    pl.table = l0::align256(static_cast<size_t>(count) * sizeof(l0_problem));
+    pl.order_bytes = l0::align256(static_cast<size_t>(count) * sizeof(int32_t));
+    pl.counters = l0::align256(pl.groups.size() * sizeof(int32_t));
+    pl.scratch = scratch;
+    pl.total = pl.table + pl.order_bytes + pl.counters + pl.scratch;
+    return true;
+}
+
+struct Candidate {
+    int block_threads, words_cap;
+};
+const Candidate kCandidates[] = {{256, 8192}, {256, 16384}, {512, 16384}, {512, 32768}};
+
+void resolve(const l0_batch_opts* o, int& bt, int& wc) {
+    bt = (o && o->block_threads) ? o->block_threads : 256;
+    wc = (o && o->words_cap) ? o->words_cap : 8192;
+}
+
+l0_status launch_batch(const l0_problem* probs, int32_t count, const l0_batch_opts* opts, const BatchPlan& pl,
+                       l0_result* results, char* ws, hipStream_t stream) {
+    const l0_problem* table = reinterpret_cast<const l0_problem*>(ws);
+    const int32_t* order = reinterpret_cast<const int32_t*>(ws + pl.table);
+    unsigned* counters = reinterpret_cast<unsigned*>(ws + pl.table + pl.order_bytes);
+    char* scratch = ws + pl.table + pl.order_bytes + pl.counters;
+    hipError_t e = hipMemcpyAsync(const_cast<l0_problem*>(table), probs, sizeof(l0_problem) * count,
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(const_cast<int32_t*>(order), pl.order.data(), sizeof(int32_t) * count,
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = l0::launch_zero(reinterpret_cast<int32_t*>(counters), static_cast<int64_t>(pl.groups.size()), stream);
+    for (size_t gi = 0; gi < pl.groups.size() && e == hipSuccess; ++gi) {
+        const Group& g = pl.groups[gi];
+        l0::BatchParams bp{};
+        bp.probs = table;
+        bp.order = order + g.start;
+        bp.count = g.count;
+        bp.rule = opts ? opts->rule : L0_RULE_L0DEC;
+        bp.tol_mode = opts ? opts->tol_mode : L0_TOL_RELATIVE;
+        bp.words_cap = g.words_cap;
+        bp.stage_d = g.d;
+        bp.results = results;
+        bp.scratch = scratch;
+        bp.lay = g.lay;
+        bp.next = counters + gi;
+        bp.timing = opts ? opts->timing : nullptr;
+        void* args[] = {&bp};
+        e = hipLaunchKernel(l0::batch_kernel_fn(pl.block_threads, g.range), dim3(static_cast<unsigned>(g.grid)),
+                            dim3(static_cast<unsigned>(pl.block_threads)), args, g.lds, stream);
+    }
+    return from_hip(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t l0_batch_workspace_bytes(const l0_problem* probs, int32_t count, const l0_batch_opts* opts) {
+    if (!batch_opts_ok(opts)) return 0;
+    BatchPlan base;
+    if (!problems_ok(probs, count, base, false)) return 0;
+    if (opts) {
+        int bt, wc;
+        resolve(opts, bt, wc);
+        BatchPlan pl = base;
+        return plan_batch(count, bt, wc, pl) ? pl.total : 0;
+    }
+    size_t best = 0;
+    for (const Candidate& c : kCandidates) {
+        BatchPlan pl = base;
+        if (plan_batch(count, c.block_threads, c.words_cap, pl)) best = std::max(best, pl.total);
+    }
+    return best;
+}
+
+l0_status l0_decode_batched(const l0_problem* probs, int32_t count, const l0_batch_opts* opts,
+                            l0_result* results, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    if (!batch_opts_ok(opts)) return L0_ERR_ARG;
+    BatchPlan pl;
+    if (!problems_ok(probs, count, pl, true)) return L0_ERR_ARG;
+    if (!buffer_ok(results, sizeof(l0_result) * static_cast<size_t>(count))) return L0_ERR_ARG;
+    if (opts && opts->timing && !buffer_ok(opts->timing, 8 * sizeof(int64_t) * static_cast<size_t>(count)))
+        return L0_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return L0_ERR_ARG;
+    int bt, wc;
+    resolve(opts, bt, wc);
+    if (!plan_batch(count, bt, wc, pl)) return L0_ERR_ARG;
+    if (ws_bytes < pl.total) return L0_ERR_WORKSPACE;
+    if (!buffer_ok(workspace, pl.total)) return L0_ERR_ARG;
+    return launch_batch(probs, count, opts, pl, results, static_cast<char*>(workspace), stream);
+}
+
+l0_status l0_batch_autotune(const l0_problem* probs, int32_t count, l0_batch_opts* opts, l0_result* results,
+                            void* workspace, size_t ws_bytes, hipStream_t stream) {
+    if (!opts || !batch_opts_ok(opts)) return L0_ERR_ARG;
+    BatchPlan base;
+    if (!problems_ok(probs, count, base, true)) return L0_ERR_ARG;
+    if (!buffer_ok(results, sizeof(l0_result) * static_cast<size_t>(count))) return L0_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return L0_ERR_ARG;
+    // a spread sample: every s-th instance of the processing order
+    const std::vector<int32_t>& ord = base.order;
+    const int32_t want = std::min<int32_t>(count, 256);
+    const int32_t step = std::max<int32_t>(1, count / want);
+    std::vector<l0_problem> sample;
+    for (int32_t q = 0; q < count && static_cast<int32_t>(sample.size()) < want; q += step) sample.push_back(probs[ord[q]]);
+    const int32_t sc = static_cast<int32_t>(sample.size());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return L0_ERR_HIP;
+    float best_ms = -1.0f;
+    Candidate best{0, 0};
+    l0_status st = L0_OK;
+    for (const Candidate& c : kCandidates) {
+        BatchPlan pl;
+        if (!problems_ok(sample.data(), sc, pl, false) || !plan_batch(sc, c.block_threads, c.words_cap, pl)) continue;
+        if (pl.total > ws_bytes || !buffer_ok(workspace, pl.total)) continue;
+        l0_batch_opts o = *opts;
+        o.timing = nullptr;
+        o.block_threads = c.block_threads;
+        o.words_cap = c.words_cap;
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2 && st == L0_OK; ++rep) {
+            if (hipEventRecord(e0, stream) != hipSuccess) { st = L0_ERR_HIP; break; }
+            st = launch_batch(sample.data(), sc, &o, pl, results, static_cast<char*>(workspace), stream);
+            if (st != L0_OK) break;
+            if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = L0_ERR_HIP;
+                break;
+            }
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) { st = L0_ERR_HIP; break; }
+            ms = std::min(ms, t);
+        }
+        if (st != L0_OK) break;
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != L0_OK) return st;
+    if (best_ms < 0.0f) return L0_ERR_WORKSPACE;
+    opts->block_threads = best.block_threads;
+    opts->words_cap = best.words_cap;
+    return L0_OK;
+}
+
+}  // extern "C"

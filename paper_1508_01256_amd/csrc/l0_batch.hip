@@ -1,0 +1,612 @@
+// Batched Parallel-l0: many independent instances of uneven (n, m, d), as in
+// the phase-transition sweeps of the paper's Section 5.
+//
+// One persistent launch per range of column degrees.  A workgroup owns one
+// instance at a time and takes the next one from a device counter, in the
+// host-given order (largest first).  Every phase of Algorithm 2 for that instance runs
+// inside the workgroup, so a workgroup barrier separates vote, residual
+// update and control; instances never wait for each other.  The vote streams
+// the caller's column-index store directly: each wave keeps several 64-column
+// groups of indices in flight and transposes each group through LDS.  Row
+// bucket words (l0_filter.h) sit in LDS when the instance's m fits the
+// launch's word capacity.  Scoring, updates and residual recomputation are
+// the single-instance decoder's (l0_filter.h, l0_common.h), so every
+// instance's result is bitwise the one it gets alone.
+//
+// Every pointer into device memory is typed as a global-memory pointer: a
+// generic pointer would compile to flat accesses, whose completion the LDS
+// waits of the vote also wait for.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "l0_batch.h"
+#include "l0_common.h"
+#include "l0_filter.h"
+
+namespace l0 {
+
+namespace {
+
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> global(T* p) {
+    return (gptr<T>)p;
+}
+
+// LDS pointers are typed too: the per-degree solvers are separate functions,
+// which could not otherwise tell LDS from global addresses.
+template <class T>
+using lptr = __attribute__((address_space(3))) T*;
+
+// LDS queue of columns passing the filter: kBatchQueue entries split evenly
+// over the waves, each wave's segment followed by 64 per-lane discard slots.
+constexpr int kBatchQueue = 2048;
+
+// Per-instance state in the workgroup's scratch (fields named as the
+// single-instance solver's, for apply_update / row_residual).
+struct BlockState {
+    gptr<double> x;
+    gptr<const double> y;
+    gptr<double> r;
+    gptr<uint32_t> rword;
+    gptr<uint32_t> member;
+    gptr<int32_t> slot_cnt;
+    gptr<int32_t> slot_sorted;
+    gptr<int32_t> aff_flag;
+    gptr<int32_t> aff_list;
+    gptr<int32_t> long_rows;
+    gptr<int32_t> row_off;
+    gptr<int32_t> slots;
+    gptr<int32_t> overflow;
+};
+
+__device__ BlockState carve(const BatchParams& bp, const l0_problem& P) {
+    char* base = bp.scratch + static_cast<size_t>(blockIdx.x) * bp.lay.stride;
+    BlockState s{};
+    s.x = global(P.x_out);
+    s.y = global(P.y);
+    s.r = global(reinterpret_cast<double*>(base + bp.lay.r));
+    s.rword = global(reinterpret_cast<uint32_t*>(base + bp.lay.rword));
+    s.member = global(reinterpret_cast<uint32_t*>(base + bp.lay.member));
+    s.slot_cnt = global(reinterpret_cast<int32_t*>(base + bp.lay.slot_cnt));
+    s.slot_sorted = global(reinterpret_cast<int32_t*>(base + bp.lay.slot_sorted));
+    s.aff_flag = global(reinterpret_cast<int32_t*>(base + bp.lay.aff_flag));
+    s.aff_list = global(reinterpret_cast<int32_t*>(base + bp.lay.aff_list));
+    s.long_rows = global(reinterpret_cast<int32_t*>(base + bp.lay.long_rows));
+    s.row_off = global(reinterpret_cast<int32_t*>(base + bp.lay.row_off));
+    s.slots = global(reinterpret_cast<int32_t*>(base + bp.lay.slots));
+    s.overflow = global(reinterpret_cast<int32_t*>(base + bp.lay.overflow));
+    return s;
+}
+
+// Workgroup-wide sum; valid in every thread.  `red` holds one int per wave.
+__device__ int wg_sum(int v, lptr<int> red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int t = 0;
+    for (int w = 0; w < nw; ++w) t += red[w];
+    return t;
+}
+
+__device__ double wg_max(double v, lptr<double> red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    const int nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t = fmax(t, red[w]);
+    return t;
+}
+
+// Exclusive prefix sum of a[0..len) (LDS) plus carry into out[0..len);
+// returns the new carry.  All threads call it.
+__device__ int wg_scan_to(lptr<const int> a, int len, gptr<int32_t> out, int carry, lptr<int> red) {
+    const int nw = blockDim.x >> 6, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int base = 0; base < len; base += blockDim.x) {
+        const int i = base + threadIdx.x;
+        const int v = i < len ? a[i] : 0;
+        int incl = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off);
+            if (lane >= off) incl += o;
+        }
+        __syncthreads();
+        if (lane == 63) red[wid] = incl;
+        __syncthreads();
+        int before = carry;
+        for (int w = 0; w < wid; ++w) before += red[w];
+        if (i < len) out[i] = before + incl - v;
+        int total = carry;
+        for (int w = 0; w < nw; ++w) total += red[w];
+        carry = total;
+    }
+    return carry;
+}
+
+struct Lds {
+    lptr<uint32_t> words;  // words_cap entries (also the degree histogram)
+    lptr<int> stage;       // (blockDim/64) * 64 * D entries
+    lptr<int> queue;       // kBatchQueue + (blockDim/64) * 64 entries
+    lptr<int> red;         // 16 ints / 8 doubles of reduction scratch
+    lptr<int> ctr;         // [0] tcount [1] affc [2] support [4] spilled count [5] long rows
+    lptr<int> wq;          // per-wave queue counts (16)
+};
+
+// Indices of 64-column group g (64*D consecutive ints, lane-strided).  The
+// address is clamped into the array, so the load is unconditional (no branch
+// for the wait counters to merge over); entries past the end belong to
+// columns j >= n, which never pass.
+template <int D>
+__device__ __forceinline__ void load_group(gptr<const int32_t> col_idx, int64_t g, int64_t nd, int lane,
+                                           int (&out)[D]) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int64_t e = g * 64 * D + k * 64 + lane;
+        out[k] = col_idx[e < nd ? e : nd - 1];
+    }
+}
+
+// One vote pass over all columns.  SPILL = false: each wave appends the
+// columns passing the bucket filter to its LDS queue segment and counts them
+// in wq[wave], also past the segment's capacity (those are not kept).
+// SPILL = true: every passing column goes to the global list, counted in
+// ctr[4]; this pass runs only after some segment overflowed.
+//
+// The ordinary pass has no branch and no global write in its loop body:
+// either would make the compiler drain all outstanding loads at the loop
+// head, serialising the index prefetch.  Lanes with nothing to queue store
+// to their discard slot instead.  WL: bucket words in LDS, else in global
+// memory.  Each wave handles groups wid, wid + nw, ... in rounds of kDepth
+// slots; slots past the last group run on clamped indices and queue nothing.
+template <int D, bool WL, bool SPILL>
+__device__ void vote_pass(gptr<const int32_t> col_idx, int64_t n, const BlockState& s, const Lds& L, int a,
+                          int rule) {
+    // groups in flight per wave: about 32 registers of indices
+    constexpr int kDepth = D <= 8 ? 4 : (D <= 10 ? 3 : (D <= 16 ? 2 : 1));
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    // the wave index is uniform across the wave: a scalar loop (no exec mask)
+    const int wid = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int qcap = kBatchQueue / nw;
+    const lptr<int> seg = L.queue + wid * (qcap + 64);
+    const int64_t nd = n * D;
+    const int64_t ngroups = (n + 63) >> 6;
+    const lptr<int> stage = L.stage + wid * (64 * D);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int count = 0;  // wave-uniform
+    int buf[kDepth][D];
+#pragma unroll
+    for (int sl = 0; sl < kDepth; ++sl) load_group<D>(col_idx, wid + sl * nw, nd, lane, buf[sl]);
+    for (int64_t g0 = wid; g0 < ngroups; g0 += kDepth * nw) {
+#pragma unroll
+        for (int sl = 0; sl < kDepth; ++sl) {
+            const int64_t g = g0 + sl * nw;
+#pragma unroll
+            for (int k = 0; k < D; ++k) stage[k * 64 + lane] = buf[sl][k];
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+            __builtin_amdgcn_wave_barrier();
+            uint32_t w[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                const int row = stage[lane * D + t];
+                w[t] = WL ? L.words[row] : s.rword[row];
+            }
+            // refill this slot after the gathers are issued (the scheduler may
+            // not hoist it): the gathers never wait for it, and it is in
+            // flight while the filter runs
+            __builtin_amdgcn_sched_barrier(0);
+            load_group<D>(col_idx, g + kDepth * nw, nd, lane, buf[sl]);
+            __builtin_amdgcn_wave_barrier();
+            const int64_t j = g * 64 + lane;
+            const bool pass = bucket_filter<D>(w, a, rule) && j < n;
+            const unsigned long long mask = __ballot(pass);
+            if (SPILL) {
+                if (mask) {
+                    int qb = 0;
+                    if (lane == 0) qb = fetch_add(&L.ctr[4], __popcll(mask));
+                    qb = __shfl(qb, 0);
+                    if (pass) s.overflow[qb + __popcll(mask & below)] = static_cast<int>(j);
+                }
+            } else {
+                const int pos = count + __popcll(mask & below);
+                seg[(pass && pos < qcap) ? pos : qcap + lane] = static_cast<int>(j);
+                count += __popcll(mask);
+            }
+        }
+    }
+    if (!SPILL && lane == 0) L.wq[wid] = count;
+}
+
+// The vote of one iteration.  Returns the number of queued columns; *spilled
+// tells whether they are in the global list (else in the wave segments).
+template <int D, bool WL>
+__device__ int vote(gptr<const int32_t> col_idx, int64_t n, const BlockState& s, const Lds& L, int a, int rule,
+                    bool* spilled) {
+    const int nw = blockDim.x >> 6, qcap = kBatchQueue / nw;
+    vote_pass<D, WL, false>(col_idx, n, s, L, a, rule);
+    __syncthreads();
+    int total = 0;
+    bool over = false;
+    for (int w = 0; w < nw; ++w) {
+        total += L.wq[w];
+        over |= L.wq[w] > qcap;
+    }
+    *spilled = over;
+    if (!over) return total;
+    vote_pass<D, WL, true>(col_idx, n, s, L, a, rule);
+    __syncthreads();
+    return L.ctr[4];
+}
+
+// The q-th queued column of the wave segments (counts wq[0..nw)).
+__device__ __forceinline__ int queued(const Lds& L, int q) {
+    const int nw = blockDim.x >> 6, qcap = kBatchQueue / nw;
+    int w = 0;
+    while (q >= L.wq[w]) q -= L.wq[w++];
+    return L.queue[w * (qcap + 64) + q];
+}
+
+template <int D>
+__device__ void score_column(gptr<const int32_t> col_idx, const BlockState& s, int rule, lptr<int> ctr, int64_t j,
+                             double tau, int a) {
+    int rows[D];
+    double v[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) rows[t] = col_idx[j * D + t];
+#pragma unroll
+    for (int t = 0; t < D; ++t) v[t] = s.r[rows[t]];
+    double w;
+    if (exact_score<D>(v, tau, rule, a, w)) apply_update<D>(s, &ctr[0], &ctr[2], &ctr[1], j, w, rows);
+}
+
+__device__ void write_result(gptr<l0_result> res, int iters, int outcome, int nnz, int support,
+                             long long updates) {
+    res->iters = iters;
+    res->outcome = outcome;
+    res->final_nnz = nnz;
+    res->support_size = support;
+    res->updates = updates;
+}
+
+// Store the new residual of row i (and its bucket word); returns the change
+// of the row's nonzero indicator.
+__device__ __forceinline__ int finish_row(const BlockState& s, const Lds& L, bool wl, int i, double rn, double tau,
+                                          double inv_w) {
+    const bool was = fabs(s.r[i]) > tau;
+    const bool now = fabs(rn) > tau;
+    s.r[i] = rn;
+    const uint32_t w = row_word(rn, tau, inv_w);
+    s.rword[i] = w;
+    if (wl) L.words[i] = w;
+    s.aff_flag[i] = 0;
+    return static_cast<int>(now) - static_cast<int>(was);
+}
+
+// Longest support list sorted in LDS; longer ones are sorted in place in
+// global memory.
+constexpr int kLongList = 1024;
+static_assert(kLongList + 2 * 512 <= kBatchQueue, "long-list buffers live in the queue region");
+
+// Ascending sort of buf[0..cnt) by the whole workgroup: the bitonic network
+// in its direction-free form (each block of k first compares mirrored pairs
+// t and t ^ (k - 1), then the half-cleaners t and t ^ j), with pairs past
+// cnt skipped, which acts as padding with +infinity.  GLOBAL: buf is in
+// global memory; every step then ends with an acquire of the other threads'
+// stores.
+template <bool GLOBAL, class Ptr>
+__device__ void wg_sort(Ptr buf, int cnt) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    int p2 = 1;
+    while (p2 < cnt) p2 <<= 1;
+    for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int mask = (j == (k >> 1)) ? k - 1 : j;
+            for (int t = tid; t < p2; t += nthr) {
+                const int l = t ^ mask;
+                if (l > t && l < cnt) {
+                    const int a = buf[t], b = buf[l];
+                    if (a > b) {
+                        buf[t] = b;
+                        buf[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+            if (GLOBAL) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+    }
+}
+
+// row_residual for one row with a long support list, computed by the whole
+// workgroup (every thread calls it; the result is valid in thread 0): the
+// list is sorted (in LDS when it fits, else in place) when it has unsorted
+// entries, then x_hat is gathered 512 entries at a time into LDS and thread
+// 0 adds them in ascending j from +0.0.
+__device__ double long_row_residual(const BlockState& s, const Lds& L, int i) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int cnt = s.slot_cnt[i];
+    const auto list = s.slots + s.row_off[i];
+    const bool sorted = s.slot_sorted[i] == cnt;
+    const bool in_lds = cnt <= kLongList;
+    const lptr<int> sb = L.queue;
+    const lptr<double> xb = (lptr<double>)(L.queue + kLongList);
+    if (in_lds) {
+        for (int t = tid; t < cnt; t += nthr) sb[t] = list[t];
+        __syncthreads();
+        if (!sorted) {
+            wg_sort<false>(sb, cnt);
+            for (int t = tid; t < cnt; t += nthr) list[t] = sb[t];
+        }
+    } else if (!sorted) {
+        wg_sort<true>(list, cnt);
+    }
+    __syncthreads();
+    if (tid == 0 && !sorted) s.slot_sorted[i] = cnt;
+    double sum = 0.0;
+    for (int c0 = 0; c0 < cnt; c0 += 512) {
+        const int len = min(512, cnt - c0);
+        for (int t = tid; t < len; t += nthr) xb[t] = s.x[in_lds ? sb[c0 + t] : list[c0 + t]];
+        __syncthreads();
+        if (tid == 0)
+            for (int t = 0; t < len; ++t) sum += xb[t];
+        __syncthreads();
+    }
+    return s.y[i] - sum;
+}
+
+// Device clock (constant 100 MHz), read by thread 0 for the optional
+// per-instance timing record.
+__device__ __forceinline__ int64_t stamp() {
+    return static_cast<int64_t>(wall_clock64());
+}
+
+// Not inlined: each degree gets its own register allocation inside the
+// range kernels (the call costs one register save per instance).
+template <int D>
+__device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchParams& bp_in, const Lds& L_in,
+                                            l0_result* res_in, int64_t* tim_in) {
+    // copies of the arguments: read once, then never reloaded in the loops
+    // (through the references they could alias any store)
+    const l0_problem P = P_in;
+    const BatchParams bp = bp_in;
+    const Lds L = L_in;
+    const gptr<l0_result> res = global(res_in);
+    const gptr<int64_t> tim = tim_in ? global(tim_in) : nullptr;
+    const BlockState s = carve(bp, P);
+    const gptr<const int32_t> col_idx = global(P.col_idx);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int64_t n = P.n;
+    const int m = P.m;
+    const int64_t nd = n * D;
+    const bool wl = m <= bp.words_cap;
+    const lptr<int> ctr = L.ctr;
+
+    // --- init: x_hat = 0, support bitmap, per-row state, r = y, max |y|
+    for (int64_t j = tid; j < n; j += nthr) s.x[j] = 0.0;
+    for (int64_t w = tid; w < ((n + 31) >> 5); w += nthr) s.member[w] = 0u;
+    double lmax = 0.0;
+    int bad = 0;
+    for (int i = tid; i < m; i += nthr) {
+        const double yi = s.y[i];
+        if (!isfinite(yi)) bad = 1;
+        else lmax = fmax(lmax, fabs(yi));
+        s.r[i] = yi;
+        s.slot_cnt[i] = 0;
+        s.slot_sorted[i] = 0;
+        s.aff_flag[i] = 0;
+    }
+    // --- row degrees -> row_off (exclusive scan), counted in LDS one range
+    //     of words_cap rows at a time; the index stream is read kHistUnroll
+    //     independent loads per thread at a time.  Every row index is
+    //     range-checked in the first pass.
+    int bad_idx = 0;
+    const int hcap = bp.words_cap;
+    const lptr<int> hist = (lptr<int>)L.words;
+    constexpr int kHistUnroll = 16;
+    int carry = 0;
+    for (int lo = 0; lo < m; lo += hcap) {
+        const int len = min(hcap, m - lo);
+        for (int i = tid; i < len; i += nthr) hist[i] = 0;
+        __syncthreads();
+        for (int64_t base = 0; base < nd; base += static_cast<int64_t>(nthr) * kHistUnroll) {
+            int rows[kHistUnroll];
+#pragma unroll
+            for (int u = 0; u < kHistUnroll; ++u) {
+                const int64_t e = base + static_cast<int64_t>(u) * nthr + tid;
+                rows[u] = col_idx[e < nd ? e : nd - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kHistUnroll; ++u) {
+                const int64_t e = base + static_cast<int64_t>(u) * nthr + tid;
+                const int rel = rows[u] - lo;
+                if (lo == 0) bad_idx |= rows[u] < 0 || rows[u] >= m;
+                if (e < nd && rel >= 0 && rel < len) fetch_add(&hist[rel], 1);
+            }
+        }
+        __syncthreads();
+        carry = wg_scan_to(hist, len, s.row_off + lo, carry, L.red);
+        __syncthreads();
+    }
+    if (tid == 0) s.row_off[m] = carry;
+    const double ymax = wg_max(lmax, (lptr<double>)L.red);
+    const int nbad = wg_sum(bad, L.red);
+    const int nbadi = wg_sum(bad_idx, L.red);
+    if (nbad || nbadi) {
+        if (tid == 0) write_result(res, 0, nbadi ? L0_DEV_BAD_INDEX : L0_DEV_NONFINITE_Y, 0, 0, 0);
+        __syncthreads();
+        return;
+    }
+    const double tau = (bp.tol_mode == L0_TOL_RELATIVE) ? P.tol * ymax : P.tol;
+    const double inv_w = 1.0 / bucket_width(tau, ymax);
+    const int a = static_cast<int>(ceil(P.alpha));
+    int nzc = 0;
+    for (int i = tid; i < m; i += nthr) {
+        const double yi = s.y[i];
+        const uint32_t w = row_word(yi, tau, inv_w);
+        s.rword[i] = w;
+        if (wl) L.words[i] = w;
+        nzc += fabs(yi) > tau;
+    }
+    int nnz = wg_sum(nzc, L.red);
+    if (tid == 0) ctr[2] = 0;
+    __syncthreads();
+    int64_t t_last = 0, t_vote = 0, t_score = 0, t_resid = 0;
+    if (tim && tid == 0) {
+        t_last = stamp();
+        tim[2] = t_last - tim[0];
+    }
+
+    int l = 0, outcome;
+    long long updates = 0;
+    for (;;) {
+        if (nnz == 0) { outcome = L0_CONVERGED; break; }
+        if (l == P.max_iter) { outcome = L0_MAX_ITER; break; }
+        if (tid == 0) { ctr[0] = 0; ctr[1] = 0; ctr[4] = 0; ctr[5] = 0; }
+        __syncthreads();
+
+        bool spilled;
+        const int qn = wl ? vote<D, true>(col_idx, n, s, L, a, bp.rule, &spilled)
+                          : vote<D, false>(col_idx, n, s, L, a, bp.rule, &spilled);
+        if (tim && tid == 0) {
+            const int64_t t = stamp();
+            t_vote += t - t_last;
+            t_last = t;
+        }
+
+        // exact scores of the columns that passed (from the wave segments, or
+        // from the global list after an overflow); Jacobi updates
+        for (int q = tid; q < qn; q += nthr) {
+            const int j = spilled ? s.overflow[q] : queued(L, q);
+            score_column<D>(col_idx, s, bp.rule, ctr, j, tau, a);
+        }
+        __syncthreads();
+        if (tim && tid == 0) {
+            const int64_t t = stamp();
+            t_score += t - t_last;
+            t_last = t;
+        }
+        const int tc = ctr[0];
+        if (tc == 0) { outcome = L0_STALLED; break; }
+
+        // residual update of the touched rows; ||r||_0 by its change.
+        // Support-list counts were raised by device-scope atomics: acquire
+        // before reading them.  Short lists are handled one row per thread,
+        // long ones by the whole workgroup afterwards.
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int na = ctr[1];
+        int delta = 0;
+        for (int q = tid; q < na; q += nthr) {
+            const int i = s.aff_list[q];
+            const int cnt = s.slot_cnt[i];
+            if (cnt <= kShortList) delta += finish_row(s, L, wl, i, row_residual_short(s, i, cnt), tau, inv_w);
+            else s.long_rows[fetch_add(&ctr[5], 1)] = i;
+        }
+        __syncthreads();
+        const int nl = ctr[5];
+        for (int li = 0; li < nl; ++li) {
+            const int i = s.long_rows[li];
+            const double rn = long_row_residual(s, L, i);
+            if (tid == 0) delta += finish_row(s, L, wl, i, rn, tau, inv_w);
+        }
+        nnz += wg_sum(delta, L.red);
+        updates += tc;
+        ++l;
+        if (tim && tid == 0) {
+            const int64_t t = stamp();
+            t_resid += t - t_last;
+            t_last = t;
+        }
+    }
+    if (tid == 0) write_result(res, l, outcome, nnz, ctr[2], updates);
+    if (tim && tid == 0) {
+        tim[3] = t_vote;
+        tim[4] = t_score;
+        tim[5] = t_resid;
+    }
+    __syncthreads();
+}
+
+template <int D, int DHI>
+__device__ void solve_dispatch(const l0_problem& P, const BatchParams& bp, const Lds& L, l0_result* res,
+                               int64_t* tim) {
+    if constexpr (D > DHI) {
+        return;
+    } else {
+        if (P.d == D) solve_instance<D>(P, bp, L, res, tim);
+        else solve_dispatch<D + 1, DHI>(P, bp, L, res, tim);
+    }
+}
+
+// One kernel per range of degrees [DLO, DHI] (kBatchRanges): instances of
+// all degrees of a range share one persistent launch, so a sweep over
+// several degrees is not split into launches that each wait for their
+// slowest instance.
+template <int BS, int DLO, int DHI>
+__global__ void __launch_bounds__(BS) batch_kernel(BatchParams bp) {
+    extern __shared__ uint32_t lds[];
+    __shared__ double red[16];  // reduction scratch, read as int or double
+    __shared__ int ctr[8];
+    __shared__ int wq[16];
+    __shared__ int s_inst;
+    Lds L;
+    L.words = (lptr<uint32_t>)lds;
+    L.stage = (lptr<int>)(lds + bp.words_cap);
+    L.queue = L.stage + (BS / 64) * 64 * bp.stage_d;
+    L.red = (lptr<int>)red;
+    L.ctr = (lptr<int>)ctr;
+    L.wq = (lptr<int>)wq;
+    for (;;) {
+        if (threadIdx.x == 0) s_inst = static_cast<int>(atomicAdd(bp.next, 1u));
+        __syncthreads();
+        const int q = s_inst;
+        __syncthreads();
+        if (q >= bp.count) break;
+        const int inst = bp.order[q];
+        const l0_problem P = bp.probs[inst];
+        int64_t* tim = bp.timing ? bp.timing + 8 * static_cast<int64_t>(inst) : nullptr;
+        if (tim && threadIdx.x == 0) {
+            tim[0] = stamp();
+            for (int k = 1; k < 6; ++k) tim[k] = 0;
+            tim[6] = blockIdx.x;
+            tim[7] = 0;
+        }
+        solve_dispatch<DLO, DHI>(P, bp, L, &bp.results[inst], tim);
+        if (tim && threadIdx.x == 0) tim[1] = stamp();
+    }
+}
+
+template <int BS, int R = 0>
+const void* kernel_for(int range) {
+    if constexpr (R >= kBatchRangeCount) {
+        return nullptr;
+    } else {
+        return range == R ? reinterpret_cast<const void*>(&batch_kernel<BS, kBatchRanges[R][0], kBatchRanges[R][1]>)
+                          : kernel_for<BS, R + 1>(range);
+    }
+}
+
+}  // namespace
+
+size_t batch_lds_bytes(int block_threads, int words_cap, int d) {
+    const size_t waves = static_cast<size_t>(block_threads / 64);
+    return static_cast<size_t>(words_cap) * 4 + waves * 64 * d * 4 + (kBatchQueue + waves * 64) * 4;
+}
+
+const void* batch_kernel_fn(int block_threads, int range) {
+    switch (block_threads) {
+        case 256: return kernel_for<256>(range);
+        case 512: return kernel_for<512>(range);
+        default: return nullptr;
+    }
+}
+
+}  // namespace l0

@@ -1,0 +1,127 @@
+// Device helpers shared by the single-instance and the batched decoders:
+// applying one selected update (Algorithm 2's x_hat_j += omega) and
+// recomputing one residual entry (r <- y - A x_hat, row by row).  The state
+// record's pointers may be generic or typed global-memory pointers; the
+// atomics are the relaxed, device-scope operations of HIP's atomicAdd,
+// atomicOr and atomicExch, written so that they accept either.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <climits>
+#include <stdint.h>
+
+namespace l0 {
+
+// Number of lanes of this wave with `pred`, in every lane (wave ballot).
+__device__ __forceinline__ int wave_count(bool pred) {
+    return __popcll(__ballot(pred));
+}
+
+template <class Ptr, class V>
+__device__ __forceinline__ V fetch_add(Ptr p, V v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Apply x_hat_j += w for a selected column j with rows rows[0..D): count it in
+// *tcount, enter j into the support (bitmap; on first entry append j to each
+// row's support list and count it in *support), and record every row it
+// touches once in the touched-row list (count in *affc).  S provides x,
+// member, slot_cnt, slots, row_off, aff_flag, aff_list.
+template <int D, class S, class C>
+__device__ void apply_update(const S& p, C tcount, C support, C affc, int64_t j, double w,
+                             const int (&rows)[D]) {
+    p.x[j] = p.x[j] + w;
+    fetch_add(tcount, 1);
+    const uint32_t bit = 1u << (j & 31);
+    const uint32_t old = __hip_atomic_fetch_or(&p.member[j >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool fresh = (old & bit) == 0;
+    if (fresh) fetch_add(support, 1);
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        const int i = rows[t];
+        if (fresh) {
+            const int q = fetch_add(&p.slot_cnt[i], 1);
+            p.slots[p.row_off[i] + q] = static_cast<int>(j);
+        }
+        if (__hip_atomic_exchange(&p.aff_flag[i], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            const int q = fetch_add(affc, 1);
+            p.aff_list[q] = i;
+        }
+    }
+}
+
+// r_i = y_i - (sum over the support columns of row i, ascending, of x_hat_j).
+// The row's list holds its support columns; entries appended since the last
+// visit are merged into the sorted prefix first.
+template <class S>
+__device__ double row_residual(const S& p, int i) {
+    const auto list = p.slots + p.row_off[i];
+    const int cnt = p.slot_cnt[i];
+    const int done = p.slot_sorted[i];
+    for (int q = done; q < cnt; ++q) {
+        const int v = list[q];
+        int k = q;
+        while (k > 0 && list[k - 1] > v) {
+            list[k] = list[k - 1];
+            --k;
+        }
+        list[k] = v;
+    }
+    if (done != cnt) p.slot_sorted[i] = cnt;
+    double s = 0.0;
+    for (int q = 0; q < cnt; ++q) s += p.x[list[q]];
+    return p.y[i] - s;
+}
+
+// Support lists of at most this many entries are sorted in registers.
+constexpr int kShortList = 16;
+
+// Ascending bitonic sorting network over N (a power of two) register values.
+template <int N>
+__device__ __forceinline__ void sort_network(int (&v)[N]) {
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int a = v[i], b = v[l];
+                    const bool up = (i & k) == 0;
+                    v[i] = up ? min(a, b) : max(a, b);
+                    v[l] = up ? max(a, b) : min(a, b);
+                }
+            }
+        }
+    }
+}
+
+// row_residual for a row whose support list holds cnt <= kShortList
+// entries: the list is sorted in registers (and written back) when it has
+// unsorted entries, x_hat is gathered for all entries at once, and the sum
+// still runs in ascending j from +0.0.
+template <class S>
+__device__ double row_residual_short(const S& p, int i, int cnt) {
+    const auto list = p.slots + p.row_off[i];
+    int v[kShortList];
+#pragma unroll
+    for (int q = 0; q < kShortList; ++q) v[q] = q < cnt ? list[q] : INT_MAX;
+    if (p.slot_sorted[i] != cnt) {
+        sort_network<kShortList>(v);
+#pragma unroll
+        for (int q = 0; q < kShortList; ++q)
+            if (q < cnt) list[q] = v[q];
+        p.slot_sorted[i] = cnt;
+    }
+    double xv[kShortList];
+#pragma unroll
+    for (int q = 0; q < kShortList; ++q) xv[q] = q < cnt ? p.x[v[q]] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kShortList; ++q)
+        if (q < cnt) s += xv[q];
+    return p.y[i] - s;
+}
+
+}  // namespace l0

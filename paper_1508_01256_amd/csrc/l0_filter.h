@@ -169,7 +169,9 @@ L0_HD bool bucket_filter(const uint32_t (&w)[D], int a, int rule) {
 #pragma unroll
     for (int k = 0; k < L; ++k) z |= static_cast<int>(c[k] >> 31) << k;
     const int need = a + (rule == kRuleL0dec ? z : 0);
-    if (need > D) return false;
+    // need > D can never be met; tested without a branch (the comparison
+    // below only sees need's low L bits then, and its result is discarded)
+    const bool reachable = need <= D;
     uint32_t ge = 0u, eq = 0xFFFFFFFFu;
 #pragma unroll
     for (int k = L - 1; k >= 0; --k) {
@@ -177,7 +179,7 @@ L0_HD bool bucket_filter(const uint32_t (&w)[D], int a, int rule) {
         ge |= eq & c[k] & ~tb;
         eq &= ~(c[k] ^ tb);
     }
-    return ((ge | eq) & kBucketBits) != 0u;
+    return reachable & (((ge | eq) & kBucketBits) != 0u);
 }
 
 

@@ -116,4 +116,10 @@ hipError_t launch_prepare(const int32_t* col_idx, const MatrixView& A, int check
 // Enqueue one solve (control reset + the persistent cooperative kernel).
 hipError_t launch_solve(const SolveParams& p, hipStream_t s);
 
+// Enqueue a fill of count int32 zeros (a kernel, so it may sit in graphs).
+hipError_t launch_zero(int32_t* p, int64_t count, hipStream_t s);
+
+// Compute units of the current device (0 if unknown).
+int device_cus();
+
 }  // namespace l0

@@ -20,6 +20,7 @@
 
 #include "l0_internal.h"
 #include "l0_filter.h"
+#include "l0_common.h"
 
 static_assert(l0::kRuleL0dec == L0_RULE_L0DEC && l0::kRuleMode == L0_RULE_MODE, "rule codes");
 
@@ -144,11 +145,6 @@ __device__ int block_sum(int v) {
     return s_total;
 }
 
-// Number of lanes of this wave with `pred`, in every lane (wave ballot).
-__device__ __forceinline__ int wave_count(bool pred) {
-    return __popcll(__ballot(pred));
-}
-
 __device__ __forceinline__ int64_t soa_index(int64_t j, int t, int d) {
     return ((j / kTile) * d + t) * kTile + (j % kTile);
 }
@@ -175,28 +171,6 @@ __device__ void write_result(const SolveParams& p, int iters, int outcome, int n
 // the score of one column (eq. (selection_l0))
 // ---------------------------------------------------------------------------
 
-template <int D>
-__device__ void apply_update(const SolveParams& p, int l, int64_t j, double w, const int (&rows)[D]) {
-    p.x[j] = p.x[j] + w;
-    atomicAdd(&p.tcount[l], 1);
-    const uint32_t bit = 1u << (j & 31);
-    const uint32_t old = atomicOr(&p.member[j >> 5], bit);
-    const bool fresh = (old & bit) == 0;
-    if (fresh) atomicAdd(&p.ctrl->support, 1);
-#pragma unroll
-    for (int t = 0; t < D; ++t) {
-        const int i = rows[t];
-        if (fresh) {
-            const int q = atomicAdd(&p.slot_cnt[i], 1);
-            p.slots[p.row_off[i] + q] = static_cast<int>(j);
-        }
-        if (atomicExch(&p.aff_flag[i], 1) == 0) {
-            const int q = atomicAdd(&p.affc[l], 1);
-            p.aff_list[q] = i;
-        }
-    }
-}
-
 // Exact scoring of one column that passed the bucket filter: its rows come
 // from the repacked index store, its values from the FP64 residual.
 template <int D, bool COMPACT>
@@ -208,7 +182,8 @@ __device__ void score_exact(const SolveParams& p, int l, int64_t j, double tau) 
 #pragma unroll
     for (int t = 0; t < D; ++t) v[t] = p.r[rows[t]];
     double w;
-    if (exact_score<D>(v, tau, p.rule, p.a, w)) apply_update<D>(p, l, j, w, rows);
+    if (exact_score<D>(v, tau, p.rule, p.a, w))
+        apply_update<D>(p, &p.tcount[l], &p.ctrl->support, &p.affc[l], j, w, rows);
 }
 
 constexpr int kQueue = 2048;  // per-workgroup queue of columns passing the filter
@@ -307,28 +282,6 @@ __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32
         if (p.timeline && blockIdx.x == 0)
             p.timeline[3 * p.max_iter + 10 + 3 * l] = static_cast<int64_t>(wall_clock64());
     }
-}
-
-// r_i = y_i - (sum over the support columns of row i, ascending, of x_hat_j).
-// The row's list holds its support columns; entries appended since the last
-// visit are merged into the sorted prefix first.
-__device__ double row_residual(const SolveParams& p, int i) {
-    int* list = p.slots + p.row_off[i];
-    const int cnt = p.slot_cnt[i];
-    const int done = p.slot_sorted[i];
-    for (int q = done; q < cnt; ++q) {
-        const int v = list[q];
-        int k = q;
-        while (k > 0 && list[k - 1] > v) {
-            list[k] = list[k - 1];
-            --k;
-        }
-        list[k] = v;
-    }
-    if (done != cnt) p.slot_sorted[i] = cnt;
-    double s = 0.0;
-    for (int q = 0; q < cnt; ++q) s += p.x[list[q]];
-    return p.y[i] - s;
 }
 
 // ---------------------------------------------------------------------------
@@ -609,14 +562,22 @@ __global__ void __launch_bounds__(1024) scan_kernel(MatrixView A) {
 // host-side launchers
 // ---------------------------------------------------------------------------
 
-namespace {
-
 int device_cus() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     return cus;
 }
+
+hipError_t launch_zero(int32_t* p, int64_t count, hipStream_t s) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(zero_ints, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+namespace {
 
 uint64_t barrier_limit_ticks() {
     int dev = 0, khz = 0;

@@ -68,3 +68,31 @@ def run_both(inst_or_arrays, **kw):
     g = gpu_run(*args, **kw)
     o = oracle_run(*args, **kw)
     return g, o
+
+
+def batched_run(insts, *, alphas=None, max_iters=None, tol=1e-10, rule=l0.L0_RULE_L0DEC,
+                tol_mode=l0.L0_TOL_RELATIVE, block_threads=0, words_cap=0, autotune=False):
+    """Decode Instances (or (n, m, d, col, y, alpha) tuples) in one
+    l0_decode_batched call; returns one dict per instance (x as numpy)."""
+    probs = []
+    for q, i in enumerate(insts):
+        n, m, d, col, y, a = (i.n, i.m, i.d, i.col_idx, i.y, i.alpha) if hasattr(i, "col_idx") else i
+        probs.append(dict(col_idx=to_dev(col, torch.int32), n=n, m=m, d=d,
+                          y=to_dev(y, torch.float64),
+                          alpha=a if alphas is None else alphas[q],
+                          max_iter=100 if max_iters is None else max_iters[q], tol=tol))
+    xs, res = l0.decode_batched(probs, rule=rule, tol_mode=tol_mode, block_threads=block_threads,
+                                words_cap=words_cap, autotune=autotune)
+    for x, r in zip(xs, res):
+        r["x"] = x.cpu().numpy()
+    return res
+
+
+def assert_batched_parity(b, o, *, label=""):
+    """A batched result against the oracle: outcome, iterations, final
+    ||r||_0, total updates and x_hat bitwise."""
+    assert b["outcome"] == o["outcome"], (label, b["outcome"], o["outcome"])
+    assert b["iters"] == o["iters"], (label, b["iters"], o["iters"])
+    assert b["final_nnz"] == int(o["trace"][-1]), (label, b["final_nnz"], o["trace"][-1])
+    assert b["updates"] == int(np.sum(o["tsize"])), (label, b["updates"], o["tsize"])
+    assert np.array_equal(b["x"].view(np.int64), o["x"].view(np.int64)), (label, "x_hat differs")

@@ -86,3 +86,87 @@ def test_bad_options_and_handles():
 def test_status_strings():
     assert "CONVERGED" in l0.l0_status_string(0)
     assert l0.l0_status_string(l0.L0_DEV_BAD_INDEX) == "L0_DEV_BAD_INDEX"
+
+
+def _table(**over):
+    p = dict(col_idx=None, n=4096, m=512, d=7, y=None, alpha=4.0, max_iter=10, reserved=0,
+             tol=1e-10, x_out=None)
+    p.update(over)
+    arr = (l0.l0_problem * 2)()
+    arr[0] = l0.l0_problem(None, 4096, 512, 7, None, 4.0, 10, 0, 1e-10, None)
+    arr[1] = l0.l0_problem(p["col_idx"], p["n"], p["m"], p["d"], p["y"], p["alpha"], p["max_iter"],
+                           p["reserved"], p["tol"], p["x_out"])
+    return arr
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=0), dict(m=0), dict(d=1), dict(d=21), dict(d=9, m=8), dict(alpha=1.0), dict(alpha=7.5),
+    dict(max_iter=-1), dict(tol=float("nan")), dict(reserved=1),
+])
+def test_batched_argument_errors(bad):
+    L = l0.lib()
+    t = _table(**bad)
+    assert L.l0_batch_workspace_bytes(t, 2, None) == 0
+    assert L.l0_decode_batched(t, 2, None, None, None, 0, None) == l0.L0_ERR_ARG
+    o = l0.l0_batch_opts()
+    assert L.l0_batch_autotune(t, 2, ctypes.byref(o), None, None, 0, None) == l0.L0_ERR_ARG
+
+
+def test_batched_bad_options_and_counts():
+    L = l0.lib()
+    t = _table()
+    # null device buffers are rejected before any device work
+    assert L.l0_decode_batched(t, 2, None, None, None, 0, None) == l0.L0_ERR_ARG
+    assert L.l0_decode_batched(None, 2, None, None, None, 0, None) == l0.L0_ERR_ARG
+    assert L.l0_decode_batched(t, 0, None, None, None, 0, None) == l0.L0_ERR_ARG
+    assert L.l0_batch_workspace_bytes(t, 0, None) == 0
+    for o in [l0.l0_batch_opts(rule=2), l0.l0_batch_opts(tol_mode=2),
+              l0.l0_batch_opts(block_threads=128), l0.l0_batch_opts(block_threads=1024),
+              l0.l0_batch_opts(words_cap=-1), l0.l0_batch_opts(words_cap=63),
+              l0.l0_batch_opts(words_cap=40000)]:
+        assert L.l0_batch_workspace_bytes(t, 2, ctypes.byref(o)) == 0
+        assert L.l0_decode_batched(t, 2, ctypes.byref(o), None, None, 0, None) == l0.L0_ERR_ARG
+    # autotune needs an options record to write into
+    assert L.l0_batch_autotune(t, 2, None, None, None, 0, None) == l0.L0_ERR_ARG
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes records have the C compiler's sizes and field offsets."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "l0decode.h"\n'
+        '#define F(T, f) printf(#T " " #f " %zu\\n", offsetof(T, f));\n'
+        'int main(void) {\n'
+        '  printf("l0_opts %zu\\n", sizeof(l0_opts));\n'
+        '  printf("l0_problem %zu\\n", sizeof(l0_problem));\n'
+        '  printf("l0_batch_opts %zu\\n", sizeof(l0_batch_opts));\n'
+        '  printf("l0_result %zu\\n", sizeof(l0_result));\n'
+        '  F(l0_problem, n) F(l0_problem, m) F(l0_problem, d) F(l0_problem, y) F(l0_problem, alpha)\n'
+        '  F(l0_problem, max_iter) F(l0_problem, tol) F(l0_problem, x_out)\n'
+        '  F(l0_opts, x_init) F(l0_opts, timeline) F(l0_batch_opts, words_cap)\n'
+        '  F(l0_batch_opts, timing)\n'
+        '  F(l0_result, updates)\n'
+        '  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", f"-I{os.path.join(ROOT, 'include')}",
+                    "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        parts = line.split()
+        if len(parts) == 2:
+            got[parts[0]] = int(parts[1])
+        elif len(parts) == 3:
+            got[parts[0] + "." + parts[1]] = int(parts[2])
+    assert got["l0_opts"] == ctypes.sizeof(l0.l0_opts)
+    assert got["l0_problem"] == ctypes.sizeof(l0.l0_problem)
+    assert got["l0_batch_opts"] == ctypes.sizeof(l0.l0_batch_opts)
+    assert got["l0_result"] == 24  # the binding's int64[3] result records
+    for name, cls in [("l0_problem", l0.l0_problem), ("l0_opts", l0.l0_opts),
+                      ("l0_batch_opts", l0.l0_batch_opts)]:
+        for f, _ in cls._fields_:
+            key = f"{name}.{f}"
+            if key in got:
+                assert got[key] == getattr(cls, f).offset, key
+    assert got["l0_result.updates"] == 16

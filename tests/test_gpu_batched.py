@@ -1,0 +1,179 @@
+"""GPU parity of the batched decoder (l0_decode_batched), called through the
+C-ABI: every instance of a batch against the CPU oracle (outcome, iterations,
+final ||r||_0, update count, x_hat bitwise) and against its own solo run."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import paper_1508_01256_amd as l0
+from parity import assert_batched_parity, batched_run, gpu_run, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    l0.lib()
+
+
+def sweep_like(count, seed, n_max_log2=14):
+    """Instances shaped like the phase-transition sweep (mixed n, delta, d
+    in {5, 7, 9}, rho), with n capped so the oracle finishes in seconds."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        n = int(round(2.0 ** rng.uniform(6.0, n_max_log2)))
+        delta = float(rng.choice([0.01, 0.03, 0.1, 0.3]))
+        d = int(rng.choice([5, 7, 9]))
+        m = max(gen.mk_m(n, delta), d)
+        k = gen.mk_k(m, float(rng.uniform(0.05, 0.5)))
+        out.append(gen.make_instance(seed * 7919 + i, n, m, d, k))
+    return out
+
+
+def check_all(insts, res, label, **kw):
+    for q, (i, b) in enumerate(zip(insts, res)):
+        o = oracle_run(i.n, i.m, i.d, i.col_idx, i.y, kw.get("alphas", [i.alpha] * len(insts))[q],
+                       max_iter=kw.get("max_iters", [100] * len(insts))[q],
+                       rule=kw.get("rule", l0.L0_RULE_L0DEC))
+        assert_batched_parity(b, o, label=f"{label}/{q} n={i.n} m={i.m} d={i.d} k={i.k}")
+
+
+@pytest.mark.parametrize("bt,wc", [(0, 0), (512, 16384), (256, 64)])
+def test_mixed_batch_against_oracle(bt, wc):
+    insts = sweep_like(160, 11)
+    say("batched mixed", bt, wc, len(insts))
+    res = batched_run(insts, block_threads=bt, words_cap=wc)
+    check_all(insts, res, f"mixed-{bt}-{wc}")
+
+
+def test_batch_matches_solo_runs():
+    insts = sweep_like(40, 12)
+    res = batched_run(insts)
+    for q, (i, b) in enumerate(zip(insts, res)):
+        g = gpu_run(i.n, i.m, i.d, i.col_idx, i.y, i.alpha)
+        for key in ("iters", "outcome", "final_nnz", "support_size", "updates"):
+            assert b[key] == g[key], (q, key, b[key], g[key])
+        assert np.array_equal(b["x"].view(np.int64), g["x"].view(np.int64)), q
+
+
+def test_edge_instances():
+    """k = 0, one column, m = d, tiny m with d = 9, largest and smallest d,
+    a column past a 64-column group, and instances whose m exceeds the LDS
+    word capacity, all in one batch (several degree groups)."""
+    insts = [
+        gen.make_instance(1, 4096, 512, 7, 0),
+        gen.make_instance(2, 1, 3, 2, 1),
+        gen.make_instance(3, 50, 9, 9, 2),
+        gen.make_instance(4, 200, 10, 9, 1),
+        gen.make_instance(5, 3000, 600, 20, 20),
+        gen.make_instance(6, 3000, 300, 2, 10),
+        gen.make_instance(7, 65, 30, 3, 3),
+        gen.make_instance(8, 60000, 12000, 7, 900),   # m above an 8192-word capacity
+        gen.make_instance(9, 40000, 36000, 5, 900),
+        gen.make_instance(10, 64, 20, 4, 2),
+    ]
+    res = batched_run(insts, words_cap=8192)
+    check_all(insts, res, "edge")
+    assert res[0]["outcome"] == l0.L0_CONVERGED and res[0]["iters"] == 0
+
+
+def test_rules_alpha_and_max_iter():
+    insts = sweep_like(48, 13, n_max_log2=13)
+    alphas = [float(2 + (q % 3)) if i.d >= 4 else 2.0 for q, i in enumerate(insts)]
+    alphas = [min(a, float(i.d)) for a, i in zip(alphas, insts)]
+    iters = [q % 4 for q in range(len(insts))]  # 0..3: many stop at MAX_ITER
+    for rule in (l0.L0_RULE_L0DEC, l0.L0_RULE_MODE):
+        res = batched_run(insts, alphas=alphas, max_iters=iters, rule=rule)
+        check_all(insts, res, f"rule{rule}", alphas=alphas, max_iters=iters, rule=rule)
+
+
+def test_absolute_tolerance():
+    insts = sweep_like(24, 14, n_max_log2=12)
+    tol = 2.0 ** -30
+    res = batched_run(insts, tol=tol, tol_mode=l0.L0_TOL_ABSOLUTE)
+    exact = 0
+    for q, (i, b) in enumerate(zip(insts, res)):
+        g = gpu_run(i.n, i.m, i.d, i.col_idx, i.y, i.alpha, tol=tol, tol_mode=l0.L0_TOL_ABSOLUTE)
+        for key in ("iters", "outcome", "final_nnz", "support_size", "updates"):
+            assert b[key] == g[key], (q, key)
+        assert np.array_equal(b["x"].view(np.int64), g["x"].view(np.int64)), q
+        # the oracle takes a relative tolerance: compare where it converts exactly
+        s = float(np.max(np.abs(i.y))) if i.m else 0.0
+        if s > 0 and tol / s * s == tol:
+            o = oracle_run(i.n, i.m, i.d, i.col_idx, i.y, i.alpha, tol=tol,
+                           tol_mode=l0.L0_TOL_ABSOLUTE)
+            assert_batched_parity(b, o, label=f"abs/{q}")
+            exact += 1
+    say("absolute-tolerance instances checked against the oracle:", exact)
+
+
+def test_per_instance_device_errors():
+    """A bad row index or a non-finite y fails only its own instance."""
+    insts = sweep_like(12, 15, n_max_log2=12)
+    bad_col = insts[3].col_idx.copy()
+    bad_col[5] = insts[3].m          # one row index out of range
+    bad_y = insts[7].y.copy()
+    bad_y[0] = np.nan
+    arrs = [(i.n, i.m, i.d, i.col_idx, i.y, i.alpha) for i in insts]
+    arrs[3] = (insts[3].n, insts[3].m, insts[3].d, bad_col, insts[3].y, insts[3].alpha)
+    arrs[7] = (insts[7].n, insts[7].m, insts[7].d, insts[7].col_idx, bad_y, insts[7].alpha)
+    res = batched_run(arrs)
+    assert res[3]["outcome"] == l0.L0_DEV_BAD_INDEX
+    assert res[7]["outcome"] == l0.L0_DEV_NONFINITE_Y
+    for q, i in enumerate(insts):
+        if q in (3, 7):
+            continue
+        o = oracle_run(i.n, i.m, i.d, i.col_idx, i.y, i.alpha)
+        assert_batched_parity(res[q], o, label=f"err/{q}")
+
+
+def test_autotune_then_decode():
+    insts = sweep_like(64, 16, n_max_log2=13)
+    res = batched_run(insts, autotune=True)
+    check_all(insts, res, "autotuned")
+
+
+def test_two_batches_in_a_row_reuse_nothing_stale():
+    """A second, smaller batch after a first (same process, fresh workspace
+    contents left by the first) gives its own oracle results."""
+    a = sweep_like(30, 17, n_max_log2=13)
+    b = sweep_like(9, 18, n_max_log2=11)
+    batched_run(a)
+    res = batched_run(b)
+    check_all(b, res, "second")
+
+
+def test_sweep_workload_full_size_sampled():
+    """The full phase-transition sweep's instance mix at its real sizes
+    (n up to 2^18) in one batched call; a spread sample is checked against the
+    oracle, every instance against the invariants of its outcome."""
+    params = gen.sweep_params(4096)
+    idx = list(range(0, 4096, 8))   # 512 instances, every size class
+    insts = [gen.make_instance(params[i]["seed"], params[i]["n"], params[i]["m"], params[i]["d"],
+                               params[i]["k"]) for i in idx]
+    say("sweep sample", len(insts))
+    res = batched_run(insts)
+    for q in range(0, len(insts), 4):   # 128 oracle runs
+        i = insts[q]
+        o = oracle_run(i.n, i.m, i.d, i.col_idx, i.y, i.alpha)
+        assert_batched_parity(res[q], o, label=f"sweep/{idx[q]}")
+    for b in res:
+        assert b["outcome"] in (l0.L0_CONVERGED, l0.L0_STALLED, l0.L0_MAX_ITER)
+        assert (b["final_nnz"] == 0) == (b["outcome"] == l0.L0_CONVERGED)
+
+
+def test_long_support_lists():
+    """Tiny m with d = 9: a first iteration selects most columns, so row
+    support lists grow to hundreds of entries (sorted in LDS) and, at
+    n = 4000, past the LDS sort's capacity (the one-thread path)."""
+    insts = [gen.make_instance(31, 1030, 10, 9, 3), gen.make_instance(32, 1046, 10, 9, 4),
+             gen.make_instance(33, 4000, 10, 9, 3), gen.make_instance(34, 2000, 20, 9, 5),
+             gen.make_instance(35, 6931, 69, 7, 15)]
+    res = batched_run(insts)
+    check_all(insts, res, "long-lists")
+    g = gpu_run(insts[2].n, insts[2].m, insts[2].d, insts[2].col_idx, insts[2].y, insts[2].alpha)
+    assert res[2]["support_size"] == g["support_size"]
