@@ -88,6 +88,12 @@ def main():
     ap.add_argument("--repeats", type=int, default=30, help="l0_solve launches timed for the roofline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--kind", choices=["normal", "pm1"], default="normal")
+    ap.add_argument("--workload", choices=["single", "sweep"], default="single",
+                    help="single: one n=2^24 instance (default); sweep: 4096 phase-transition "
+                         "instances through the batched decoder")
+    ap.add_argument("--sweep-count", type=int, default=4096)
+    ap.add_argument("--autotune", action="store_true", help="sweep: pick the schedule with "
+                    "l0_batch_autotune first")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches) to calibrate "
                          "rocprofv3 byte counters, then exit")
@@ -113,6 +119,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes_each_way": a.numel() * 4, "launches": 3}))
         return
+    if args.workload == "sweep":
+        return sweep(args)
     kind = gen.VALUES_NORMAL if args.kind == "normal" else gen.VALUES_PM1
     t0 = time.time()
     inst = gen.single_workload("n2^24", 0, kind=kind)
@@ -246,6 +254,160 @@ def main():
                    "vote_bytes_per_pass": vote_bytes, "prepare_ms": round(prep_ms, 3),
                    "solves_per_s_prepared": round(1e3 / solve_avg, 3),
                    "phase_us": phases_us},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def solve_bytes(n, m, d, iters, outcome, tsizes):
+    """Algorithmic bytes of one decode with 32-bit indices: 8n (x_hat zeroed)
+    plus, per vote pass, 4nd + 16m + (16 + 4d)|T|."""
+    passes = passes_of(iters, outcome)
+    return 8 * n + passes * (4 * n * d + 16 * m) + sum((16 + 4 * d) * t for t in tsizes)
+
+
+def sweep(args):
+    """Batched phase-transition sweep: all instances in one l0_decode_batched
+    call per step, against a plain loop of one l0_decode_ex per instance."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1508_01256_amd as l0
+
+    count = args.sweep_count
+    params = gen.sweep_params(4096)[:count]
+    t0 = time.time()
+    insts = [gen.make_instance(p["seed"], p["n"], p["m"], p["d"], p["k"]) for p in params]
+    dev = "cuda"
+    probs = [dict(col_idx=torch.from_numpy(i.col_idx).to(dev), n=i.n, m=i.m, d=i.d,
+                  y=torch.from_numpy(i.y).to(dev), alpha=i.alpha, max_iter=100, tol=1e-10,
+                  x_out=torch.empty(i.n, dtype=torch.float64, device=dev)) for i in insts]
+    torch.cuda.synchronize()
+    print(f"[bench] generated and uploaded {count} sweep instances in {time.time() - t0:.1f}s "
+          f"(index bytes {sum(4 * i.n * i.d for i in insts) / 1e9:.2f} GB)", file=sys.stderr, flush=True)
+    table = l0.problem_table(probs)
+    opts = l0.l0_batch_opts(0, 0, 512, 32768)
+    results = l0.new_results(count, dev)
+    if args.autotune:
+        ws = torch.empty(l0.l0_batch_workspace_bytes(table, None), dtype=torch.uint8, device=dev)
+        st = l0.l0_batch_autotune(table, opts, results, ws)
+        assert st == l0.L0_OK, st
+        print(f"[bench] autotuned schedule: {opts.block_threads} threads, {opts.words_cap} words",
+              file=sys.stderr, flush=True)
+    else:
+        ws = torch.empty(l0.l0_batch_workspace_bytes(table, opts), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        st = l0.l0_decode_batched(table, opts, results, ws)
+        if st != l0.L0_OK:
+            raise RuntimeError(f"l0_decode_batched status {st}")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    rl = l0.results_list(results)
+    xs = [p["x_out"].cpu().numpy() for p in probs]
+
+    # per-instance record of the timed configuration (one more step)
+    tim = torch.zeros((count, 8), dtype=torch.int64, device=dev)
+    topts = l0.l0_batch_opts(opts.rule, opts.tol_mode, opts.block_threads, opts.words_cap, tim.data_ptr())
+    assert l0.l0_decode_batched(table, topts, results, ws) == l0.L0_OK
+    torch.cuda.synchronize()
+    T = tim.cpu().numpy().astype(np.float64) / 100.0
+    span_us = T[:, 1].max() - T[:, 0].min()
+    phase_ms = {k: round(float(T[:, c].sum()) / 1e3, 1) for k, c in
+                (("setup", 2), ("vote", 3), ("score", 4), ("residual", 5))}
+    busy = float((T[:, 1] - T[:, 0]).sum())
+
+    # plain path: one l0_decode_ex per instance on one stream
+    mx = max(l0.l0_workspace_bytes(i.n, i.m, i.d, 100) for i in insts)
+    ws1 = torch.empty(mx, dtype=torch.uint8, device=dev)
+    r1 = l0.new_result(dev)
+    xp = [torch.empty(i.n, dtype=torch.float64, device=dev) for i in insts]
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for p, x in zip(probs, xp):
+        st = l0.l0_decode_ex(p["col_idx"], p["n"], p["m"], p["d"], p["y"], p["alpha"], 100, 1e-10,
+                             x, None, r1, ws1)
+        assert st == l0.L0_OK
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - p0
+    same = all(torch.equal(a, b["x_out"]) for a, b in zip(xp, probs))
+
+    # success (||x_hat - x||_inf <= 1e-12 ||x||_inf; k = 0: x_hat = 0) per (delta, rho-bin) cell
+    def success(i, x):
+        if i.k == 0:
+            return not np.any(x)
+        xt = i.x
+        return float(np.max(np.abs(x - xt))) <= 1e-12 * float(np.max(np.abs(xt)))
+
+    succ = [success(i, x) and r["outcome"] == l0.L0_CONVERGED for i, x, r in zip(insts, xs, rl)]
+    cells = {}
+    for p, ok in zip(params, succ):
+        key = f"delta={p['delta']:g} rho=[{int(p['rho'] / 0.05) * 0.05:.2f},{int(p['rho'] / 0.05) * 0.05 + 0.05:.2f})"
+        a, b = cells.get(key, (0, 0))
+        cells[key] = (a + int(ok), b + 1)
+
+    bytes_total = 0
+    cpu = None
+    sample = list(range(0, count, 16))
+    import oracle
+    c0 = time.perf_counter()
+    agree = 0
+    for q in sample:
+        i = insts[q]
+        o = oracle.parallel_l0(i.n, i.m, i.d, i.col_idx, i.y, i.alpha, max_iter=100, tol=1e-10)
+        agree += int(o["iters"] == rl[q]["iters"] and np.array_equal(o["x"], xs[q]))
+    cdt = time.perf_counter() - c0
+    if not args.no_cpu:
+        cpu = {"value": round(len(sample) / cdt, 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(sample)} instances (every 16th of the sweep), {cdt:.1f} s single thread; "
+                         f"{agree}/{len(sample)} bitwise equal to the batched GPU results"}
+    # algorithmic bytes: per instance, vote passes from the outcome; the |T| term is linear, so
+    # the total update count gives it exactly
+    for i, r in zip(insts, rl):
+        it, oc = r["iters"], r["outcome"]
+        bytes_total += solve_bytes(i.n, i.m, i.d, it, oc, [r["updates"]] if it else [])
+    achieved = bytes_total / (ms_per_step * 1e-3) / 1e9
+    print(f"[bench] batched {ms_per_step:.2f} ms per sweep ({count / ms_per_step * 1e3:.0f} solves/s); "
+          f"plain loop {plain_s * 1e3:.1f} ms ({count / plain_s:.0f} solves/s), same x: {same}; "
+          f"span {span_us / 1e3:.2f} ms, workgroup-busy {busy / 1e3:.0f} ms, phases {phase_ms}; "
+          f"oracle agreement {agree}/{len(sample)}", file=sys.stderr, flush=True)
+    for key in sorted(cells):
+        a, b = cells[key]
+        print(f"[bench]   {key}: {a}/{b} recovered", file=sys.stderr)
+    out = {
+        "metric": "batched Parallel-l0 solves/s on the phase-transition sweep vs a plain loop",
+        "value": round(count / ms_per_step * 1e3, 1),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{count} instances, n=round(2^U) U~U[10,18], delta in "
+                               "{0.01,0.03,0.1,0.3}, d in {5,7,9}, rho~U[0.05,0.5], alpha=ceil(d/2), "
+                               "max_iter=100, tol=1e-10, N(0,1) nonzeros",
+                   "schedule": {"block_threads": opts.block_threads, "words_cap": opts.words_cap}},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "l0::batch_kernel (all launches of one sweep)",
+                     "bytes_per_launch": bytes_total},
+        "cpu_baseline": cpu,
+        "detail": {"plain_loop_solves_per_s": round(count / plain_s, 1),
+                   "speedup_vs_plain": round(plain_s * 1e3 / ms_per_step, 2),
+                   "plain_results_identical": same, "span_ms": round(span_us / 1e3, 3),
+                   "workgroup_busy_ms": round(busy / 1e3, 1), "phase_ms": phase_ms,
+                   "recovered": int(sum(succ)),
+                   "outcomes": {l0.OUTCOME_NAMES[k]: int(sum(r["outcome"] == k for r in rl)) for k in (0, 1, 2)},
+                   "cells": {k: f"{a}/{b}" for k, (a, b) in sorted(cells.items())}},
     }
     print(json.dumps(out), flush=True)
 
