@@ -187,9 +187,10 @@ l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter,
  * Batched decoding: many independent instances (each its own A, y, sizes,
  * alpha, max_iter, tol) of Algorithm 2, as in the phase-transition sweeps of
  * the paper's experiments (Section 5).  One persistent launch per range of
- * column degrees present ([2,4], [5,9], [10,14], [15,20]); a workgroup
- * decodes one instance at a time and takes the next (largest n*d first) from
- * a device counter.  Each instance's result is
+ * column degrees present ([2,4], [5,9], [10,14], [15,20]); workgroups take
+ * work from a device counter (largest n*d first), a small instance going to
+ * one workgroup and a large one to a team of up to 32 that split its columns
+ * and rows.  Workspace covers each instance's own scratch.  Each instance's result is
  * bitwise the one l0_decode_ex gives it alone.  Instances must not share
  * x_out buffers.
  */
@@ -215,7 +216,8 @@ typedef struct {
     int64_t* timing;       /* optional device int64[8*count]; record i (in ticks of the
                               device's constant 100 MHz clock): [0] start, [1] end,
                               [2] setup, [3] vote, [4] scoring and updates, [5] residual
-                              (totals over iterations), [6] workgroup, [7] 0 */
+                              (totals over iterations), [6] workgroup of the team's
+                              leader, [7] team size (workgroups on the instance) */
 } l0_batch_opts;
 
 /*

@@ -328,25 +328,29 @@ namespace {
 // persistent launch of that range's kernel.
 struct Group {
     int range = 0;
-    int d = 0;  // largest degree in the group
-    int32_t start = 0, count = 0;  // range of the processing order
-    int64_t max_n = 0, max_nd = 0;
+    int d = 0;                         // largest degree in the group
+    int32_t inst_start = 0, inst_count = 0;  // range of the instance order
+    int32_t item_start = 0, item_count = 0;  // range of the work items
     int32_t max_m = 0;
     int words_cap = 0;
     size_t lds = 0;
     int grid = 0;
-    l0::BatchLayout lay{};
 };
 
 struct BatchPlan {
     int block_threads = 256;
     int words_cap = 8192;
-    std::vector<int32_t> order;  // by degree, then largest work (n*d) first
+    std::vector<int32_t> order;     // instances: by degree range, then largest n*d first
     std::vector<Group> groups;
-    size_t table = 0, order_bytes = 0, counters = 0, scratch = 0, total = 0;
+    std::vector<int32_t> items;     // work items of every group, in claim order
+    std::vector<int32_t> team;      // team size per instance
+    std::vector<int64_t> inst_off;  // scratch offset per instance
+    size_t table = 0, items_bytes = 0, team_bytes = 0, off_bytes = 0, counters = 0, ctl = 0, scratch = 0,
+           total = 0;
 };
 
 constexpr size_t kLdsLimit = 160 * 1024 - 1024;  // dynamic LDS bound (static use is < 1 KiB)
+constexpr int64_t kTeamUnit = int64_t(1) << 19;  // estimated cost per team member
 
 bool batch_opts_ok(const l0_batch_opts* o) {
     if (!o) return true;
@@ -357,9 +361,9 @@ bool batch_opts_ok(const l0_batch_opts* o) {
 }
 
 // Validate every instance (sizes and scalars always; buffers when asked),
-// order them and group them by degree.
+// order them, group them by degree range and lay out their scratch.
 bool problems_ok(const l0_problem* probs, int32_t count, BatchPlan& pl, bool buffers) {
-    if (!probs || count < 1) return false;
+    if (!probs || count < 1 || count >= (1 << l0::kItemInstBits)) return false;
     for (int32_t i = 0; i < count; ++i) {
         const l0_problem& P = probs[i];
         if (!sizes_ok(P.n, P.m, P.d) || !solve_args_ok(P.alpha, P.d, P.max_iter, P.tol) || P.reserved != 0)
@@ -384,47 +388,32 @@ bool problems_ok(const l0_problem* probs, int32_t count, BatchPlan& pl, bool buf
         if (pl.groups.empty() || pl.groups.back().range != range) {
             Group g;
             g.range = range;
-            g.start = q;
+            g.inst_start = q;
             pl.groups.push_back(g);
         }
         Group& g = pl.groups.back();
-        ++g.count;
+        ++g.inst_count;
         g.d = std::max(g.d, static_cast<int>(P.d));
-        g.max_n = std::max(g.max_n, P.n);
         g.max_m = std::max(g.max_m, P.m);
-        g.max_nd = std::max(g.max_nd, P.n * static_cast<int64_t>(P.d));
     }
+    pl.inst_off.resize(count);
+    size_t off = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        pl.inst_off[i] = static_cast<int64_t>(off);
+        off += l0::inst_layout(probs[i].n, probs[i].m, probs[i].n * probs[i].d).total;
+    }
+    pl.scratch = off;
     return true;
 }
 
-l0::BatchLayout batch_layout(int64_t N, int32_t M, int64_t ND) {
-    using l0::align256;
-    l0::BatchLayout L{};
-    size_t o = 0;
-    auto take = [&](size_t bytes) { const size_t at = o; o += align256(bytes); return at; };
-    L.r = take(static_cast<size_t>(M) * 8);
-    L.rword = take(static_cast<size_t>(M) * 4);
-    L.member = take(static_cast<size_t>((N + 31) / 32) * 4);
-    L.slot_cnt = take(static_cast<size_t>(M) * 4);
-    L.slot_sorted = take(static_cast<size_t>(M) * 4);
-    L.aff_flag = take(static_cast<size_t>(M) * 4);
-    L.aff_list = take(static_cast<size_t>(M) * 4);
-    L.long_rows = take(static_cast<size_t>(M) * 4);
-    L.row_off = take((static_cast<size_t>(M) + 1) * 4);
-    L.slots = take(static_cast<size_t>(ND) * 4);
-    L.overflow = take(static_cast<size_t>(N) * 4);
-    L.stride = o;
-    return L;
-}
-
-// Resident workgroups, LDS and byte layout of every degree group for one
-// schedule (block size, bucket-word capacity); false if infeasible.  Groups
-// run one after another on the stream, so they share the scratch region.
-bool plan_batch(int32_t count, int block_threads, int words_cap, BatchPlan& pl) {
+// Resident workgroups, LDS, team sizes and work items of every group for
+// one schedule (block size, bucket-word capacity); false if infeasible.
+bool plan_batch(const l0_problem* probs, int32_t count, int block_threads, int words_cap, BatchPlan& pl) {
     pl.block_threads = block_threads;
     pl.words_cap = words_cap;
     const int cus = l0::device_cus();
-    size_t scratch = 0;
+    pl.items.clear();
+    pl.team.assign(count, 1);
     for (Group& g : pl.groups) {
         // no more LDS words than the group's largest m needs
         const int64_t need = (static_cast<int64_t>(g.max_m) + 63) / 64 * 64;
@@ -444,15 +433,37 @@ bool plan_batch(int32_t count, int block_threads, int words_cap, BatchPlan& pl) 
             (void)hipGetLastError();
             return false;
         }
-        g.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(per_cu) * (cus > 0 ? cus : 1), g.count));
-        g.lay = batch_layout(g.max_n, g.max_m, g.max_nd);
-        scratch = std::max(scratch, static_cast<size_t>(g.grid) * g.lay.stride);
+        const int64_t resident = static_cast<int64_t>(per_cu) * (cus > 0 ? cus : 1);
+        // Estimated cost of an instance: its column indices, three times over
+        // when its bucket words do not fit in LDS (the vote then gathers them
+        // from global memory, about three times slower).  The group's
+        // instances are claimed most costly first, and an instance gets one
+        // team member per kTeamUnit of cost (at most kMaxTeam, never more
+        // than the resident workgroups: members wait for each other).
+        auto cost = [&](int32_t i) {
+            const int64_t nd = probs[i].n * probs[i].d;
+            return probs[i].m <= g.words_cap ? nd : 3 * nd;
+        };
+        std::stable_sort(pl.order.begin() + g.inst_start, pl.order.begin() + g.inst_start + g.inst_count,
+                         [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+        const int64_t tmax = std::min<int64_t>(l0::kMaxTeam, resident);
+        g.item_start = static_cast<int32_t>(pl.items.size());
+        for (int32_t q = g.inst_start; q < g.inst_start + g.inst_count; ++q) {
+            const int32_t i = pl.order[q];
+            const int t = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(tmax, (cost(i) + kTeamUnit - 1) / kTeamUnit)));
+            pl.team[i] = t;
+            for (int r = 0; r < t; ++r) pl.items.push_back(i | (r << l0::kItemInstBits));
+        }
+        g.item_count = static_cast<int32_t>(pl.items.size()) - g.item_start;
+        g.grid = static_cast<int>(std::min<int64_t>(resident, g.item_count));
     }
     pl.table = l0::align256(static_cast<size_t>(count) * sizeof(l0_problem));
-    pl.order_bytes = l0::align256(static_cast<size_t>(count) * sizeof(int32_t));
+    pl.items_bytes = l0::align256(pl.items.size() * sizeof(int32_t));
+    pl.team_bytes = l0::align256(static_cast<size_t>(count) * sizeof(int32_t));
+    pl.off_bytes = l0::align256(static_cast<size_t>(count) * sizeof(int64_t));
     pl.counters = l0::align256(pl.groups.size() * sizeof(int32_t));
-    pl.scratch = scratch;
-    pl.total = pl.table + pl.order_bytes + pl.counters + pl.scratch;
+    pl.ctl = static_cast<size_t>(count) * sizeof(l0::TeamCtl);
+    pl.total = pl.table + pl.items_bytes + pl.team_bytes + pl.off_bytes + pl.counters + pl.ctl + pl.scratch;
     return true;
 }
 
@@ -468,32 +479,45 @@ void resolve(const l0_batch_opts* o, int& bt, int& wc) {
 
 l0_status launch_batch(const l0_problem* probs, int32_t count, const l0_batch_opts* opts, const BatchPlan& pl,
                        l0_result* results, char* ws, hipStream_t stream) {
-    const l0_problem* table = reinterpret_cast<const l0_problem*>(ws);
-    const int32_t* order = reinterpret_cast<const int32_t*>(ws + pl.table);
-    unsigned* counters = reinterpret_cast<unsigned*>(ws + pl.table + pl.order_bytes);
-    char* scratch = ws + pl.table + pl.order_bytes + pl.counters;
-    hipError_t e = hipMemcpyAsync(const_cast<l0_problem*>(table), probs, sizeof(l0_problem) * count,
-                                  hipMemcpyHostToDevice, stream);
+    char* p = ws;
+    auto take = [&](size_t bytes) { char* at = p; p += bytes; return at; };
+    l0_problem* table = reinterpret_cast<l0_problem*>(take(pl.table));
+    int32_t* items = reinterpret_cast<int32_t*>(take(pl.items_bytes));
+    int32_t* team = reinterpret_cast<int32_t*>(take(pl.team_bytes));
+    int64_t* inst_off = reinterpret_cast<int64_t*>(take(pl.off_bytes));
+    unsigned* counters = reinterpret_cast<unsigned*>(take(pl.counters));
+    l0::TeamCtl* ctl = reinterpret_cast<l0::TeamCtl*>(take(pl.ctl));
+    char* scratch = take(pl.scratch);
+    hipError_t e = hipMemcpyAsync(table, probs, sizeof(l0_problem) * count, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(const_cast<int32_t*>(order), pl.order.data(), sizeof(int32_t) * count,
-                           hipMemcpyHostToDevice, stream);
+        e = hipMemcpyAsync(items, pl.items.data(), sizeof(int32_t) * pl.items.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
-        e = l0::launch_zero(reinterpret_cast<int32_t*>(counters), static_cast<int64_t>(pl.groups.size()), stream);
+        e = hipMemcpyAsync(team, pl.team.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(inst_off, pl.inst_off.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, stream);
+    // work counters and control blocks start at zero (a fill kernel)
+    if (e == hipSuccess)
+        e = l0::launch_zero(reinterpret_cast<int32_t*>(counters),
+                            static_cast<int64_t>((pl.counters + pl.ctl) / sizeof(int32_t)), stream);
+    const uint64_t limit = l0::wait_limit_ticks();
     for (size_t gi = 0; gi < pl.groups.size() && e == hipSuccess; ++gi) {
         const Group& g = pl.groups[gi];
         l0::BatchParams bp{};
         bp.probs = table;
-        bp.order = order + g.start;
-        bp.count = g.count;
+        bp.items = items + g.item_start;
+        bp.team = team;
+        bp.inst_off = inst_off;
+        bp.count = g.item_count;
         bp.rule = opts ? opts->rule : L0_RULE_L0DEC;
         bp.tol_mode = opts ? opts->tol_mode : L0_TOL_RELATIVE;
         bp.words_cap = g.words_cap;
         bp.stage_d = g.d;
         bp.results = results;
         bp.scratch = scratch;
-        bp.lay = g.lay;
+        bp.ctl = ctl;
         bp.next = counters + gi;
         bp.timing = opts ? opts->timing : nullptr;
+        bp.wait_limit = limit;
         void* args[] = {&bp};
         e = hipLaunchKernel(l0::batch_kernel_fn(pl.block_threads, g.range), dim3(static_cast<unsigned>(g.grid)),
                             dim3(static_cast<unsigned>(pl.block_threads)), args, g.lds, stream);
@@ -512,14 +536,11 @@ size_t l0_batch_workspace_bytes(const l0_problem* probs, int32_t count, const l0
     if (opts) {
         int bt, wc;
         resolve(opts, bt, wc);
-        BatchPlan pl = base;
-        return plan_batch(count, bt, wc, pl) ? pl.total : 0;
+        return plan_batch(probs, count, bt, wc, base) ? base.total : 0;
     }
     size_t best = 0;
-    for (const Candidate& c : kCandidates) {
-        BatchPlan pl = base;
-        if (plan_batch(count, c.block_threads, c.words_cap, pl)) best = std::max(best, pl.total);
-    }
+    for (const Candidate& c : kCandidates)
+        if (plan_batch(probs, count, c.block_threads, c.words_cap, base)) best = std::max(best, base.total);
     return best;
 }
 
@@ -534,7 +555,7 @@ l0_status l0_decode_batched(const l0_problem* probs, int32_t count, const l0_bat
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return L0_ERR_ARG;
     int bt, wc;
     resolve(opts, bt, wc);
-    if (!plan_batch(count, bt, wc, pl)) return L0_ERR_ARG;
+    if (!plan_batch(probs, count, bt, wc, pl)) return L0_ERR_ARG;
     if (ws_bytes < pl.total) return L0_ERR_WORKSPACE;
     if (!buffer_ok(workspace, pl.total)) return L0_ERR_ARG;
     return launch_batch(probs, count, opts, pl, results, static_cast<char*>(workspace), stream);
@@ -561,7 +582,9 @@ l0_status l0_batch_autotune(const l0_problem* probs, int32_t count, l0_batch_opt
     l0_status st = L0_OK;
     for (const Candidate& c : kCandidates) {
         BatchPlan pl;
-        if (!problems_ok(sample.data(), sc, pl, false) || !plan_batch(sc, c.block_threads, c.words_cap, pl)) continue;
+        if (!problems_ok(sample.data(), sc, pl, false) ||
+            !plan_batch(sample.data(), sc, c.block_threads, c.words_cap, pl))
+            continue;
         if (pl.total > ws_bytes || !buffer_ok(workspace, pl.total)) continue;
         l0_batch_opts o = *opts;
         o.timing = nullptr;

@@ -9,26 +9,83 @@
 
 namespace l0 {
 
-// Byte offsets of one workgroup's scratch (sized for the batch's largest
-// instance; a workgroup solves one instance at a time).
-struct BatchLayout {
-    size_t r, rword, member, slot_cnt, slot_sorted, aff_flag, aff_list, long_rows, row_off, slots, overflow;
-    size_t stride;
+// Byte offsets, within one instance's scratch region, of its working arrays
+// (sized by that instance alone).
+struct InstLayout {
+    size_t r, rword, member, slot_cnt, slot_sorted, aff_flag, aff_list, row_off, slots, overflow;
+    size_t total;
 };
+
+__host__ __device__ inline size_t align256_hd(size_t b) { return (b + 255) & ~size_t(255); }
+
+__host__ __device__ inline InstLayout inst_layout(int64_t n, int32_t m, int64_t nd) {
+    InstLayout L{};
+    size_t o = 0;
+    L.r = o;
+    o += align256_hd(static_cast<size_t>(m) * 8);
+    L.rword = o;
+    o += align256_hd(static_cast<size_t>(m) * 4);
+    L.member = o;
+    o += align256_hd(static_cast<size_t>((n + 31) / 32) * 4);
+    L.slot_cnt = o;
+    o += align256_hd(static_cast<size_t>(m) * 4);
+    L.slot_sorted = o;
+    o += align256_hd(static_cast<size_t>(m) * 4);
+    L.aff_flag = o;
+    o += align256_hd(static_cast<size_t>(m) * 4);
+    L.aff_list = o;  // two lists (iteration parity)
+    o += align256_hd(static_cast<size_t>(m) * 8);
+    L.row_off = o;
+    o += align256_hd((static_cast<size_t>(m) + 1) * 4);
+    L.slots = o;
+    o += align256_hd(static_cast<size_t>(nd) * 4);
+    L.overflow = o;
+    o += align256_hd(static_cast<size_t>(n) * 4);
+    L.total = o;
+    return L;
+}
+
+// Counters of one iteration shared by an instance's team.  Iteration l uses
+// ring[l % 3]; the leader clears ring[(l + 1) % 3] during iteration l.
+struct IterCounters {
+    int tcount;  // |T_l|
+    int affc;    // touched rows
+    int spill;   // columns in the shared overflow list
+    int delta;   // change of ||r||_0
+};
+
+// Control block of one instance (zeroed before the launch).
+struct alignas(256) TeamCtl {
+    int bar;      // team barrier arrivals (monotonic)
+    int abort;    // a barrier wait timed out
+    int bad;      // 1: non-finite y, 2: row index out of range
+    int nnz;      // ||y||_0
+    unsigned long long ymax_bits;  // max |y_i| (bits of a non-negative double)
+    int support;  // |support|
+    int pad0;
+    IterCounters ring[3];
+};
+
+// Work items: instance index in the low 24 bits, team member in the high 7.
+constexpr int kItemInstBits = 24;
+constexpr int kMaxTeam = 32;
 
 struct BatchParams {
     const l0_problem* probs;  // device copy of the instance table
-    const int32_t* order;     // this launch's instances, largest first
-    int32_t count;
+    const int32_t* items;     // this launch's work items, in claim order
+    const int32_t* team;      // team size per instance
+    const int64_t* inst_off;  // scratch offset per instance
+    int32_t count;            // work items in this launch
     int32_t rule;
     int32_t tol_mode;
     int32_t words_cap;        // bucket words kept in LDS when m <= words_cap
     int32_t stage_d;          // largest degree in the launch (LDS staging size)
     l0_result* results;
-    char* scratch;            // one BatchLayout per resident workgroup
-    BatchLayout lay;
+    char* scratch;            // instance scratch regions
+    TeamCtl* ctl;             // one per instance
     unsigned* next;           // work counter (zeroed before the launch)
     int64_t* timing;          // optional per-instance timing records (8 int64 each)
+    uint64_t wait_limit;      // bound of one team-barrier wait, in device clock ticks
 };
 
 // LDS bytes of the batched kernel for a block size, word capacity and degree.

@@ -1,21 +1,26 @@
 // Batched Parallel-l0: many independent instances of uneven (n, m, d), as in
 // the phase-transition sweeps of the paper's Section 5.
 //
-// One persistent launch per range of column degrees.  A workgroup owns one
-// instance at a time and takes the next one from a device counter, in the
-// host-given order (largest first).  Every phase of Algorithm 2 for that instance runs
-// inside the workgroup, so a workgroup barrier separates vote, residual
-// update and control; instances never wait for each other.  The vote streams
-// the caller's column-index store directly: each wave keeps several 64-column
-// groups of indices in flight and transposes each group through LDS.  Row
-// bucket words (l0_filter.h) sit in LDS when the instance's m fits the
-// launch's word capacity.  Scoring, updates and residual recomputation are
-// the single-instance decoder's (l0_filter.h, l0_common.h), so every
-// instance's result is bitwise the one it gets alone.
+// One persistent launch per range of column degrees.  The host cuts each
+// instance into T work items (T grows with n*d; T = 1 for most), and the
+// workgroups claim items from a device counter in the host-given order
+// (largest first), so the T items of an instance go to T workgroups at about
+// the same time: the instance's team.  A team runs every phase of Algorithm 2
+// on its instance, its members splitting the columns of the vote and the
+// rows of the residual update, and synchronises through a counter in the
+// instance's control block (a bounded wait).  Every instance has scratch of
+// its own size.
 //
-// Every pointer into device memory is typed as a global-memory pointer: a
-// generic pointer would compile to flat accesses, whose completion the LDS
-// waits of the vote also wait for.
+// The vote streams the caller's column-index store directly: each wave keeps
+// several 64-column groups of indices in flight and transposes each group
+// through LDS.  Row bucket words (l0_filter.h) sit in every member's LDS when
+// m fits the launch's word capacity.  Scoring, updates and residual
+// recomputation are the single-instance decoder's (l0_filter.h,
+// l0_common.h), so every instance's result is bitwise the one it gets alone.
+//
+// Every device pointer is typed with its address space: a generic pointer
+// would compile to flat accesses, whose completion the LDS waits of the vote
+// also wait for.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -36,17 +41,16 @@ __device__ __forceinline__ gptr<T> global(T* p) {
     return (gptr<T>)p;
 }
 
-// LDS pointers are typed too: the per-degree solvers are separate functions,
-// which could not otherwise tell LDS from global addresses.
 template <class T>
 using lptr = __attribute__((address_space(3))) T*;
 
 // LDS queue of columns passing the filter: kBatchQueue entries split evenly
-// over the waves, each wave's segment followed by 64 per-lane discard slots.
+// over the waves, each wave's segment followed by 64 per-lane discard slots
+// (after the vote, the discard slots hold this member's long-list rows).
 constexpr int kBatchQueue = 2048;
 
-// Per-instance state in the workgroup's scratch (fields named as the
-// single-instance solver's, for apply_update / row_residual).
+// Per-instance state (fields named as the single-instance solver's, for
+// apply_update / row_residual).
 struct BlockState {
     gptr<double> x;
     gptr<const double> y;
@@ -56,31 +60,49 @@ struct BlockState {
     gptr<int32_t> slot_cnt;
     gptr<int32_t> slot_sorted;
     gptr<int32_t> aff_flag;
-    gptr<int32_t> aff_list;
-    gptr<int32_t> long_rows;
+    gptr<int32_t> aff_list;   // this iteration's touched-row list
+    gptr<int32_t> aff_base;   // both lists
     gptr<int32_t> row_off;
     gptr<int32_t> slots;
     gptr<int32_t> overflow;
 };
 
-__device__ BlockState carve(const BatchParams& bp, const l0_problem& P) {
-    char* base = bp.scratch + static_cast<size_t>(blockIdx.x) * bp.lay.stride;
+__device__ BlockState carve(char* base, const l0_problem& P) {
+    const InstLayout lay = inst_layout(P.n, P.m, P.n * P.d);
     BlockState s{};
     s.x = global(P.x_out);
     s.y = global(P.y);
-    s.r = global(reinterpret_cast<double*>(base + bp.lay.r));
-    s.rword = global(reinterpret_cast<uint32_t*>(base + bp.lay.rword));
-    s.member = global(reinterpret_cast<uint32_t*>(base + bp.lay.member));
-    s.slot_cnt = global(reinterpret_cast<int32_t*>(base + bp.lay.slot_cnt));
-    s.slot_sorted = global(reinterpret_cast<int32_t*>(base + bp.lay.slot_sorted));
-    s.aff_flag = global(reinterpret_cast<int32_t*>(base + bp.lay.aff_flag));
-    s.aff_list = global(reinterpret_cast<int32_t*>(base + bp.lay.aff_list));
-    s.long_rows = global(reinterpret_cast<int32_t*>(base + bp.lay.long_rows));
-    s.row_off = global(reinterpret_cast<int32_t*>(base + bp.lay.row_off));
-    s.slots = global(reinterpret_cast<int32_t*>(base + bp.lay.slots));
-    s.overflow = global(reinterpret_cast<int32_t*>(base + bp.lay.overflow));
+    s.r = global(reinterpret_cast<double*>(base + lay.r));
+    s.rword = global(reinterpret_cast<uint32_t*>(base + lay.rword));
+    s.member = global(reinterpret_cast<uint32_t*>(base + lay.member));
+    s.slot_cnt = global(reinterpret_cast<int32_t*>(base + lay.slot_cnt));
+    s.slot_sorted = global(reinterpret_cast<int32_t*>(base + lay.slot_sorted));
+    s.aff_flag = global(reinterpret_cast<int32_t*>(base + lay.aff_flag));
+    s.aff_base = global(reinterpret_cast<int32_t*>(base + lay.aff_list));
+    s.aff_list = s.aff_base;
+    s.row_off = global(reinterpret_cast<int32_t*>(base + lay.row_off));
+    s.slots = global(reinterpret_cast<int32_t*>(base + lay.slots));
+    s.overflow = global(reinterpret_cast<int32_t*>(base + lay.overflow));
     return s;
 }
+
+struct Lds {
+    lptr<uint32_t> words;  // words_cap entries (also the degree histogram)
+    lptr<int> stage;       // (blockDim/64) * 64 * D entries
+    lptr<int> queue;       // kBatchQueue + (blockDim/64) * 64 entries
+    lptr<int> red;         // 16 ints / 8 doubles of reduction scratch
+    lptr<int> ctr;         // [0] long rows of this member [1] barrier result
+    lptr<int> wq;          // per-wave queue counts (16)
+};
+
+// This workgroup's place in its instance's team.
+struct Team {
+    gptr<TeamCtl> ctl;
+    int size;     // T
+    int rank;     // 0 .. T-1; rank 0 leads
+    int epoch;    // team barriers passed (kept equal in every thread)
+    uint64_t limit;
+};
 
 // Workgroup-wide sum; valid in every thread.  `red` holds one int per wave.
 __device__ int wg_sum(int v, lptr<int> red) {
@@ -133,14 +155,45 @@ __device__ int wg_scan_to(lptr<const int> a, int len, gptr<int32_t> out, int car
     return carry;
 }
 
-struct Lds {
-    lptr<uint32_t> words;  // words_cap entries (also the degree histogram)
-    lptr<int> stage;       // (blockDim/64) * 64 * D entries
-    lptr<int> queue;       // kBatchQueue + (blockDim/64) * 64 entries
-    lptr<int> red;         // 16 ints / 8 doubles of reduction scratch
-    lptr<int> ctr;         // [0] tcount [1] affc [2] support [4] spilled count [5] long rows
-    lptr<int> wq;          // per-wave queue counts (16)
-};
+template <class T>
+__device__ __forceinline__ T load_agent(gptr<T> p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Team barrier: every member's writes before it are visible to every member
+// after it.  Thread 0 of each member arrives on the monotonic counter and
+// waits (relaxed polling, bounded by tm.limit device-clock ticks, leaving
+// early on the abort flag).  Returns false, in every thread, when the wait
+// failed; the flag then tells every member to stop.  A team of one is a
+// workgroup barrier.
+__device__ bool team_sync(Team& tm, const Lds& L) {
+    __syncthreads();
+    if (tm.size == 1) return true;
+    ++tm.epoch;
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        fetch_add(&tm.ctl->bar, 1);
+        const int target = tm.size * tm.epoch;
+        const uint64_t t0 = wall_clock64();
+        int ok = 1;
+        while (load_agent(&tm.ctl->bar) < target) {
+            if (load_agent(&tm.ctl->abort)) {
+                ok = 0;
+                break;
+            }
+            if (wall_clock64() - t0 > tm.limit) {
+                __hip_atomic_store(&tm.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        L.ctr[1] = ok;
+    }
+    __syncthreads();
+    return L.ctr[1] != 0;
+}
 
 // Indices of 64-column group g (64*D consecutive ints, lane-strided).  The
 // address is clamped into the array, so the load is unconditional (no branch
@@ -156,21 +209,23 @@ __device__ __forceinline__ void load_group(gptr<const int32_t> col_idx, int64_t 
     }
 }
 
-// One vote pass over all columns.  SPILL = false: each wave appends the
-// columns passing the bucket filter to its LDS queue segment and counts them
-// in wq[wave], also past the segment's capacity (those are not kept).
-// SPILL = true: every passing column goes to the global list, counted in
-// ctr[4]; this pass runs only after some segment overflowed.
+// One vote pass over this member's columns: groups first, first + stride,
+// ... for wave 0, each wave of the member starting one group later.
+// SPILL = false: each wave appends the columns passing the bucket filter to
+// its LDS queue segment and counts them in wq[wave], also past the segment's
+// capacity (those are not kept).  SPILL = true: every passing column goes to
+// the team's shared global list, counted in *spill; this pass runs only
+// after a segment overflowed.
 //
 // The ordinary pass has no branch and no global write in its loop body:
 // either would make the compiler drain all outstanding loads at the loop
 // head, serialising the index prefetch.  Lanes with nothing to queue store
 // to their discard slot instead.  WL: bucket words in LDS, else in global
-// memory.  Each wave handles groups wid, wid + nw, ... in rounds of kDepth
-// slots; slots past the last group run on clamped indices and queue nothing.
+// memory.  Slots past the last group run on clamped indices and queue
+// nothing.
 template <int D, bool WL, bool SPILL>
-__device__ void vote_pass(gptr<const int32_t> col_idx, int64_t n, const BlockState& s, const Lds& L, int a,
-                          int rule) {
+__device__ void vote_pass(gptr<const int32_t> col_idx, int64_t n, const BlockState& s, const Lds& L, int a, int rule,
+                          int64_t first, int64_t stride, gptr<int> spill) {
     // groups in flight per wave: about 32 registers of indices
     constexpr int kDepth = D <= 8 ? 4 : (D <= 10 ? 3 : (D <= 16 ? 2 : 1));
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
@@ -182,14 +237,15 @@ __device__ void vote_pass(gptr<const int32_t> col_idx, int64_t n, const BlockSta
     const int64_t ngroups = (n + 63) >> 6;
     const lptr<int> stage = L.stage + wid * (64 * D);
     const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t g_first = first + wid, g_step = kDepth * stride;
     int count = 0;  // wave-uniform
     int buf[kDepth][D];
 #pragma unroll
-    for (int sl = 0; sl < kDepth; ++sl) load_group<D>(col_idx, wid + sl * nw, nd, lane, buf[sl]);
-    for (int64_t g0 = wid; g0 < ngroups; g0 += kDepth * nw) {
+    for (int sl = 0; sl < kDepth; ++sl) load_group<D>(col_idx, g_first + sl * stride, nd, lane, buf[sl]);
+    for (int64_t g0 = g_first; g0 < ngroups; g0 += g_step) {
 #pragma unroll
         for (int sl = 0; sl < kDepth; ++sl) {
-            const int64_t g = g0 + sl * nw;
+            const int64_t g = g0 + sl * stride;
 #pragma unroll
             for (int k = 0; k < D; ++k) stage[k * 64 + lane] = buf[sl][k];
             __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
@@ -204,7 +260,7 @@ __device__ void vote_pass(gptr<const int32_t> col_idx, int64_t n, const BlockSta
             // not hoist it): the gathers never wait for it, and it is in
             // flight while the filter runs
             __builtin_amdgcn_sched_barrier(0);
-            load_group<D>(col_idx, g + kDepth * nw, nd, lane, buf[sl]);
+            load_group<D>(col_idx, g + g_step, nd, lane, buf[sl]);
             __builtin_amdgcn_wave_barrier();
             const int64_t j = g * 64 + lane;
             const bool pass = bucket_filter<D>(w, a, rule) && j < n;
@@ -212,7 +268,7 @@ __device__ void vote_pass(gptr<const int32_t> col_idx, int64_t n, const BlockSta
             if (SPILL) {
                 if (mask) {
                     int qb = 0;
-                    if (lane == 0) qb = fetch_add(&L.ctr[4], __popcll(mask));
+                    if (lane == 0) qb = fetch_add(spill, __popcll(mask));
                     qb = __shfl(qb, 0);
                     if (pass) s.overflow[qb + __popcll(mask & below)] = static_cast<int>(j);
                 }
@@ -226,38 +282,9 @@ __device__ void vote_pass(gptr<const int32_t> col_idx, int64_t n, const BlockSta
     if (!SPILL && lane == 0) L.wq[wid] = count;
 }
 
-// The vote of one iteration.  Returns the number of queued columns; *spilled
-// tells whether they are in the global list (else in the wave segments).
-template <int D, bool WL>
-__device__ int vote(gptr<const int32_t> col_idx, int64_t n, const BlockState& s, const Lds& L, int a, int rule,
-                    bool* spilled) {
-    const int nw = blockDim.x >> 6, qcap = kBatchQueue / nw;
-    vote_pass<D, WL, false>(col_idx, n, s, L, a, rule);
-    __syncthreads();
-    int total = 0;
-    bool over = false;
-    for (int w = 0; w < nw; ++w) {
-        total += L.wq[w];
-        over |= L.wq[w] > qcap;
-    }
-    *spilled = over;
-    if (!over) return total;
-    vote_pass<D, WL, true>(col_idx, n, s, L, a, rule);
-    __syncthreads();
-    return L.ctr[4];
-}
-
-// The q-th queued column of the wave segments (counts wq[0..nw)).
-__device__ __forceinline__ int queued(const Lds& L, int q) {
-    const int nw = blockDim.x >> 6, qcap = kBatchQueue / nw;
-    int w = 0;
-    while (q >= L.wq[w]) q -= L.wq[w++];
-    return L.queue[w * (qcap + 64) + q];
-}
-
 template <int D>
-__device__ void score_column(gptr<const int32_t> col_idx, const BlockState& s, int rule, lptr<int> ctr, int64_t j,
-                             double tau, int a) {
+__device__ void score_column(gptr<const int32_t> col_idx, const BlockState& s, int rule, gptr<TeamCtl> ctl,
+                             gptr<IterCounters> ring, int64_t j, double tau, int a) {
     int rows[D];
     double v[D];
 #pragma unroll
@@ -265,16 +292,35 @@ __device__ void score_column(gptr<const int32_t> col_idx, const BlockState& s, i
 #pragma unroll
     for (int t = 0; t < D; ++t) v[t] = s.r[rows[t]];
     double w;
-    if (exact_score<D>(v, tau, rule, a, w)) apply_update<D>(s, &ctr[0], &ctr[2], &ctr[1], j, w, rows);
+    if (exact_score<D>(v, tau, rule, a, w)) apply_update<D>(s, &ring->tcount, &ctl->support, &ring->affc, j, w, rows);
 }
 
-__device__ void write_result(gptr<l0_result> res, int iters, int outcome, int nnz, int support,
-                             long long updates) {
-    res->iters = iters;
-    res->outcome = outcome;
-    res->final_nnz = nnz;
-    res->support_size = support;
-    res->updates = updates;
+// The vote of one iteration for this member, with the exact scoring of the
+// columns it queued in LDS.  Returns true when its queue overflowed: its
+// columns then went to the team's shared list, scored after a team barrier.
+template <int D, bool WL>
+__device__ bool vote_and_score(gptr<const int32_t> col_idx, int64_t n, const BlockState& s, const Lds& L, int a,
+                               int rule, const Team& tm, gptr<IterCounters> ring, double tau) {
+    const int nw = blockDim.x >> 6, qcap = kBatchQueue / nw;
+    const int64_t first = static_cast<int64_t>(tm.rank) * nw, stride = static_cast<int64_t>(tm.size) * nw;
+    vote_pass<D, WL, false>(col_idx, n, s, L, a, rule, first, stride, nullptr);
+    __syncthreads();
+    int total = 0;
+    bool over = false;
+    for (int w = 0; w < nw; ++w) {
+        total += L.wq[w];
+        over |= L.wq[w] > qcap;
+    }
+    if (over) {
+        vote_pass<D, WL, true>(col_idx, n, s, L, a, rule, first, stride, &ring->spill);
+        return true;
+    }
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+        int w = 0, k = q;
+        while (k >= L.wq[w]) k -= L.wq[w++];
+        score_column<D>(col_idx, s, rule, tm.ctl, ring, L.queue[w * (qcap + 64) + k], tau, a);
+    }
+    return false;
 }
 
 // Store the new residual of row i (and its bucket word); returns the change
@@ -363,39 +409,57 @@ __device__ double long_row_residual(const BlockState& s, const Lds& L, int i) {
     return s.y[i] - sum;
 }
 
+__device__ void write_result(gptr<l0_result> res, int iters, int outcome, int nnz, int support,
+                             long long updates) {
+    res->iters = iters;
+    res->outcome = outcome;
+    res->final_nnz = nnz;
+    res->support_size = support;
+    res->updates = updates;
+}
+
 // Device clock (constant 100 MHz), read by thread 0 for the optional
 // per-instance timing record.
 __device__ __forceinline__ int64_t stamp() {
     return static_cast<int64_t>(wall_clock64());
 }
 
-// Not inlined: each degree gets its own register allocation inside the
-// range kernels (the call costs one register save per instance).
+// One member's part of decoding instance P.  Not inlined: each degree gets
+// its own register allocation inside the range kernels (the call costs one
+// register save per work item).
 template <int D>
 __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchParams& bp_in, const Lds& L_in,
-                                            l0_result* res_in, int64_t* tim_in) {
+                                            int inst, int rank, int tsize) {
     // copies of the arguments: read once, then never reloaded in the loops
     // (through the references they could alias any store)
     const l0_problem P = P_in;
     const BatchParams bp = bp_in;
     const Lds L = L_in;
-    const gptr<l0_result> res = global(res_in);
-    const gptr<int64_t> tim = tim_in ? global(tim_in) : nullptr;
-    const BlockState s = carve(bp, P);
-    const gptr<const int32_t> col_idx = global(P.col_idx);
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const bool lead = rank == 0;
+    Team tm;
+    tm.ctl = global(bp.ctl + inst);
+    tm.size = tsize;
+    tm.rank = rank;
+    tm.epoch = 0;
+    tm.limit = bp.wait_limit;
+    const gptr<l0_result> res = global(bp.results + inst);
+    const gptr<int64_t> tim = (bp.timing && lead) ? global(bp.timing + 8 * static_cast<int64_t>(inst)) : nullptr;
+    BlockState s = carve(bp.scratch + bp.inst_off[inst], P);
+    const gptr<const int32_t> col_idx = global(P.col_idx);
     const int64_t n = P.n;
     const int m = P.m;
     const int64_t nd = n * D;
     const bool wl = m <= bp.words_cap;
-    const lptr<int> ctr = L.ctr;
+    const int64_t gt = static_cast<int64_t>(rank) * nthr + tid, gstep = static_cast<int64_t>(tsize) * nthr;
 
-    // --- init: x_hat = 0, support bitmap, per-row state, r = y, max |y|
-    for (int64_t j = tid; j < n; j += nthr) s.x[j] = 0.0;
-    for (int64_t w = tid; w < ((n + 31) >> 5); w += nthr) s.member[w] = 0u;
+    // --- init, split over the team: x_hat = 0, support bitmap, per-row
+    //     state, r = y; max |y| and non-finite y into the control block
+    for (int64_t j = gt; j < n; j += gstep) s.x[j] = 0.0;
+    for (int64_t w = gt; w < ((n + 31) >> 5); w += gstep) s.member[w] = 0u;
     double lmax = 0.0;
     int bad = 0;
-    for (int i = tid; i < m; i += nthr) {
+    for (int64_t i = gt; i < m; i += gstep) {
         const double yi = s.y[i];
         if (!isfinite(yi)) bad = 1;
         else lmax = fmax(lmax, fabs(yi));
@@ -404,145 +468,215 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         s.slot_sorted[i] = 0;
         s.aff_flag[i] = 0;
     }
+    lmax = wg_max(lmax, (lptr<double>)L.red);
+    bad = wg_sum(bad, L.red);
+    if (tid == 0) {
+        __hip_atomic_fetch_max(&tm.ctl->ymax_bits, static_cast<unsigned long long>(__double_as_longlong(lmax)),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (bad) __hip_atomic_fetch_or(&tm.ctl->bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    bool alive = team_sync(tm, L);
+
     // --- row degrees -> row_off (exclusive scan), counted in LDS one range
-    //     of words_cap rows at a time; the index stream is read kHistUnroll
-    //     independent loads per thread at a time.  Every row index is
-    //     range-checked in the first pass.
-    int bad_idx = 0;
+    //     of words_cap rows at a time over this member's share of the index
+    //     stream, read kHistUnroll independent loads per thread at a time; a
+    //     team adds its counts in slot_cnt and the leader scans.  Every row
+    //     index is range-checked in the first pass.
     const int hcap = bp.words_cap;
     const lptr<int> hist = (lptr<int>)L.words;
     constexpr int kHistUnroll = 16;
+    const int64_t e_lo = nd * rank / tsize, e_hi = nd * (rank + 1) / tsize;
+    int bad_idx = 0;
     int carry = 0;
-    for (int lo = 0; lo < m; lo += hcap) {
+    for (int lo = 0; alive && lo < m; lo += hcap) {
         const int len = min(hcap, m - lo);
         for (int i = tid; i < len; i += nthr) hist[i] = 0;
         __syncthreads();
-        for (int64_t base = 0; base < nd; base += static_cast<int64_t>(nthr) * kHistUnroll) {
+        for (int64_t base = e_lo; base < e_hi; base += static_cast<int64_t>(nthr) * kHistUnroll) {
             int rows[kHistUnroll];
 #pragma unroll
             for (int u = 0; u < kHistUnroll; ++u) {
                 const int64_t e = base + static_cast<int64_t>(u) * nthr + tid;
-                rows[u] = col_idx[e < nd ? e : nd - 1];
+                rows[u] = col_idx[e < e_hi ? e : e_hi - 1];
             }
 #pragma unroll
             for (int u = 0; u < kHistUnroll; ++u) {
                 const int64_t e = base + static_cast<int64_t>(u) * nthr + tid;
                 const int rel = rows[u] - lo;
                 if (lo == 0) bad_idx |= rows[u] < 0 || rows[u] >= m;
-                if (e < nd && rel >= 0 && rel < len) fetch_add(&hist[rel], 1);
+                if (e < e_hi && rel >= 0 && rel < len) fetch_add(&hist[rel], 1);
             }
         }
         __syncthreads();
-        carry = wg_scan_to(hist, len, s.row_off + lo, carry, L.red);
+        if (tsize == 1) {
+            carry = wg_scan_to(hist, len, s.row_off + lo, carry, L.red);
+        } else {
+            for (int i = tid; i < len; i += nthr)
+                if (hist[i]) fetch_add(&s.slot_cnt[lo + i], hist[i]);
+        }
         __syncthreads();
     }
-    if (tid == 0) s.row_off[m] = carry;
-    const double ymax = wg_max(lmax, (lptr<double>)L.red);
-    const int nbad = wg_sum(bad, L.red);
-    const int nbadi = wg_sum(bad_idx, L.red);
-    if (nbad || nbadi) {
-        if (tid == 0) write_result(res, 0, nbadi ? L0_DEV_BAD_INDEX : L0_DEV_NONFINITE_Y, 0, 0, 0);
+    bad_idx = wg_sum(bad_idx, L.red);
+    if (tid == 0 && bad_idx) __hip_atomic_fetch_or(&tm.ctl->bad, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tsize > 1) {
+        alive = alive && team_sync(tm, L);
+        if (alive && lead) {
+            const lptr<int> chunk = (lptr<int>)L.words;
+            for (int lo = 0; lo < m; lo += hcap) {
+                const int len = min(hcap, m - lo);
+                for (int i = tid; i < len; i += nthr) {
+                    chunk[i] = load_agent(&s.slot_cnt[lo + i]);
+                    s.slot_cnt[lo + i] = 0;
+                }
+                __syncthreads();
+                carry = wg_scan_to(chunk, len, s.row_off + lo, carry, L.red);
+                __syncthreads();
+            }
+        }
+    }
+    if (lead && tid == 0) s.row_off[m] = carry;
+    alive = alive && team_sync(tm, L);
+    const int flags = load_agent(&tm.ctl->bad);
+    if (!alive || flags) {
+        if (lead && tid == 0)
+            write_result(res, 0, !alive ? L0_DEV_ABORTED : ((flags & 2) ? L0_DEV_BAD_INDEX : L0_DEV_NONFINITE_Y), 0,
+                         0, 0);
         __syncthreads();
         return;
     }
+    const double ymax = __longlong_as_double(static_cast<long long>(load_agent(&tm.ctl->ymax_bits)));
     const double tau = (bp.tol_mode == L0_TOL_RELATIVE) ? P.tol * ymax : P.tol;
     const double inv_w = 1.0 / bucket_width(tau, ymax);
     const int a = static_cast<int>(ceil(P.alpha));
+    // bucket words: every member keeps all of them in LDS (when m fits);
+    // the global copy and ||y||_0 are split over the team
+    if (wl)
+        for (int i = tid; i < m; i += nthr) L.words[i] = row_word(s.y[i], tau, inv_w);
     int nzc = 0;
-    for (int i = tid; i < m; i += nthr) {
+    for (int64_t i = gt; i < m; i += gstep) {
         const double yi = s.y[i];
-        const uint32_t w = row_word(yi, tau, inv_w);
-        s.rword[i] = w;
-        if (wl) L.words[i] = w;
+        s.rword[i] = row_word(yi, tau, inv_w);
         nzc += fabs(yi) > tau;
     }
-    int nnz = wg_sum(nzc, L.red);
-    if (tid == 0) ctr[2] = 0;
-    __syncthreads();
+    nzc = wg_sum(nzc, L.red);
+    if (tid == 0) fetch_add(&tm.ctl->nnz, nzc);
+    alive = team_sync(tm, L);
+    int nnz = load_agent(&tm.ctl->nnz);
     int64_t t_last = 0, t_vote = 0, t_score = 0, t_resid = 0;
     if (tim && tid == 0) {
         t_last = stamp();
         tim[2] = t_last - tim[0];
     }
 
-    int l = 0, outcome;
+    int l = 0, outcome = L0_DEV_ABORTED;
     long long updates = 0;
-    for (;;) {
+    while (alive) {
         if (nnz == 0) { outcome = L0_CONVERGED; break; }
         if (l == P.max_iter) { outcome = L0_MAX_ITER; break; }
-        if (tid == 0) { ctr[0] = 0; ctr[1] = 0; ctr[4] = 0; ctr[5] = 0; }
+        const gptr<IterCounters> ring = &tm.ctl->ring[l % 3];
+        s.aff_list = s.aff_base + (l & 1) * m;
+        if (tid == 0) L.ctr[0] = 0;
         __syncthreads();
 
-        bool spilled;
-        const int qn = wl ? vote<D, true>(col_idx, n, s, L, a, bp.rule, &spilled)
-                          : vote<D, false>(col_idx, n, s, L, a, bp.rule, &spilled);
+        // vote and exact scoring of this member's columns (Jacobi updates)
+        const bool spilled = wl ? vote_and_score<D, true>(col_idx, n, s, L, a, bp.rule, tm, ring, tau)
+                                : vote_and_score<D, false>(col_idx, n, s, L, a, bp.rule, tm, ring, tau);
+        (void)spilled;
+        if (lead && tid == 0) {
+            const gptr<IterCounters> next = &tm.ctl->ring[(l + 1) % 3];
+            next->tcount = 0;
+            next->affc = 0;
+            next->spill = 0;
+            next->delta = 0;
+        }
         if (tim && tid == 0) {
             const int64_t t = stamp();
             t_vote += t - t_last;
             t_last = t;
         }
-
-        // exact scores of the columns that passed (from the wave segments, or
-        // from the global list after an overflow); Jacobi updates
-        for (int q = tid; q < qn; q += nthr) {
-            const int j = spilled ? s.overflow[q] : queued(L, q);
-            score_column<D>(col_idx, s, bp.rule, ctr, j, tau, a);
+        if (!(alive = team_sync(tm, L))) break;
+        // columns of overflowed queues, scored by the whole team
+        const int nsp = load_agent(&ring->spill);
+        if (nsp > 0) {
+            for (int64_t q = gt; q < nsp; q += gstep) score_column<D>(col_idx, s, bp.rule, tm.ctl, ring, s.overflow[q], tau, a);
+            if (!(alive = team_sync(tm, L))) break;
         }
-        __syncthreads();
+        // support-list counts were raised by device-scope atomics: acquire
+        // before reading them
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (tim && tid == 0) {
             const int64_t t = stamp();
             t_score += t - t_last;
             t_last = t;
         }
-        const int tc = ctr[0];
+        const int tc = load_agent(&ring->tcount);
         if (tc == 0) { outcome = L0_STALLED; break; }
 
-        // residual update of the touched rows; ||r||_0 by its change.
-        // Support-list counts were raised by device-scope atomics: acquire
-        // before reading them.  Short lists are handled one row per thread,
-        // long ones by the whole workgroup afterwards.
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const int na = ctr[1];
+        // residual update of the touched rows, split over the team; short
+        // support lists one row per thread, long ones by this whole
+        // workgroup afterwards; ||r||_0 by its change
+        const int na = load_agent(&ring->affc);
+        const int long_cap = (nthr >> 6) * 64;
+        const lptr<int> long_rows = L.queue + kBatchQueue;
         int delta = 0;
-        for (int q = tid; q < na; q += nthr) {
+        for (int64_t q = gt; q < na; q += gstep) {
             const int i = s.aff_list[q];
             const int cnt = s.slot_cnt[i];
-            if (cnt <= kShortList) delta += finish_row(s, L, wl, i, row_residual_short(s, i, cnt), tau, inv_w);
-            else s.long_rows[fetch_add(&ctr[5], 1)] = i;
+            if (cnt <= kShortList) {
+                delta += finish_row(s, L, wl, i, row_residual_short(s, i, cnt), tau, inv_w);
+            } else {
+                const int k = fetch_add(&L.ctr[0], 1);
+                if (k < long_cap) long_rows[k] = i;
+                else delta += finish_row(s, L, wl, i, row_residual(s, i), tau, inv_w);
+            }
         }
         __syncthreads();
-        const int nl = ctr[5];
+        const int nl = min(L.ctr[0], long_cap);
         for (int li = 0; li < nl; ++li) {
-            const int i = s.long_rows[li];
+            const int i = long_rows[li];
             const double rn = long_row_residual(s, L, i);
             if (tid == 0) delta += finish_row(s, L, wl, i, rn, tau, inv_w);
         }
-        nnz += wg_sum(delta, L.red);
+        delta = wg_sum(delta, L.red);
+        if (tid == 0) fetch_add(&ring->delta, delta);
+        if (!(alive = team_sync(tm, L))) break;
+        nnz += load_agent(&ring->delta);
         updates += tc;
         ++l;
+        // the other members' rows: refresh their words in this LDS copy
+        if (wl && tsize > 1) {
+            for (int q = tid; q < na; q += nthr) {
+                const int i = s.aff_list[q];
+                L.words[i] = s.rword[i];
+            }
+        }
+        __syncthreads();
         if (tim && tid == 0) {
             const int64_t t = stamp();
             t_resid += t - t_last;
             t_last = t;
         }
     }
-    if (tid == 0) write_result(res, l, outcome, nnz, ctr[2], updates);
-    if (tim && tid == 0) {
-        tim[3] = t_vote;
-        tim[4] = t_score;
-        tim[5] = t_resid;
+    if (lead && tid == 0) {
+        if (!alive) outcome = L0_DEV_ABORTED;
+        write_result(res, l, outcome, nnz, load_agent(&tm.ctl->support), updates);
+        if (tim) {
+            tim[3] = t_vote;
+            tim[4] = t_score;
+            tim[5] = t_resid;
+        }
     }
     __syncthreads();
 }
 
 template <int D, int DHI>
-__device__ void solve_dispatch(const l0_problem& P, const BatchParams& bp, const Lds& L, l0_result* res,
-                               int64_t* tim) {
+__device__ void solve_dispatch(const l0_problem& P, const BatchParams& bp, const Lds& L, int inst, int rank,
+                               int tsize) {
     if constexpr (D > DHI) {
         return;
     } else {
-        if (P.d == D) solve_instance<D>(P, bp, L, res, tim);
-        else solve_dispatch<D + 1, DHI>(P, bp, L, res, tim);
+        if (P.d == D) solve_instance<D>(P, bp, L, inst, rank, tsize);
+        else solve_dispatch<D + 1, DHI>(P, bp, L, inst, rank, tsize);
     }
 }
 
@@ -556,7 +690,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchParams bp) {
     __shared__ double red[16];  // reduction scratch, read as int or double
     __shared__ int ctr[8];
     __shared__ int wq[16];
-    __shared__ int s_inst;
+    __shared__ int s_item;
     Lds L;
     L.words = (lptr<uint32_t>)lds;
     L.stage = (lptr<int>)(lds + bp.words_cap);
@@ -565,22 +699,27 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchParams bp) {
     L.ctr = (lptr<int>)ctr;
     L.wq = (lptr<int>)wq;
     for (;;) {
-        if (threadIdx.x == 0) s_inst = static_cast<int>(atomicAdd(bp.next, 1u));
+        if (threadIdx.x == 0) {
+            const unsigned q = atomicAdd(bp.next, 1u);
+            s_item = q < static_cast<unsigned>(bp.count) ? bp.items[q] : -1;
+        }
         __syncthreads();
-        const int q = s_inst;
+        const int item = s_item;
         __syncthreads();
-        if (q >= bp.count) break;
-        const int inst = bp.order[q];
+        if (item < 0) break;
+        const int inst = item & ((1 << kItemInstBits) - 1);
+        const int rank = item >> kItemInstBits;
         const l0_problem P = bp.probs[inst];
-        int64_t* tim = bp.timing ? bp.timing + 8 * static_cast<int64_t>(inst) : nullptr;
-        if (tim && threadIdx.x == 0) {
+        const int tsize = bp.team[inst];
+        if (bp.timing && rank == 0 && threadIdx.x == 0) {
+            int64_t* tim = bp.timing + 8 * static_cast<int64_t>(inst);
             tim[0] = stamp();
             for (int k = 1; k < 6; ++k) tim[k] = 0;
             tim[6] = blockIdx.x;
-            tim[7] = 0;
+            tim[7] = tsize;
         }
-        solve_dispatch<DLO, DHI>(P, bp, L, &bp.results[inst], tim);
-        if (tim && threadIdx.x == 0) tim[1] = stamp();
+        solve_dispatch<DLO, DHI>(P, bp, L, inst, rank, tsize);
+        if (bp.timing && rank == 0 && threadIdx.x == 0) bp.timing[8 * static_cast<int64_t>(inst) + 1] = stamp();
     }
 }
 

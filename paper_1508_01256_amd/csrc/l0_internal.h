@@ -122,4 +122,7 @@ hipError_t launch_zero(int32_t* p, int64_t count, hipStream_t s);
 // Compute units of the current device (0 if unknown).
 int device_cus();
 
+// Bound of one device-side wait (20 s) in ticks of the device's constant clock.
+uint64_t wait_limit_ticks();
+
 }  // namespace l0

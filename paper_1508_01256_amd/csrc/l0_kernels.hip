@@ -681,4 +681,6 @@ hipError_t launch_prepare(const int32_t* col_idx, const MatrixView& A, int /*che
 
 hipError_t launch_solve(const SolveParams& p, hipStream_t s) { return solve_dispatch(p, s); }
 
+uint64_t wait_limit_ticks() { return barrier_limit_ticks(); }
+
 }  // namespace l0

@@ -177,3 +177,31 @@ def test_long_support_lists():
     check_all(insts, res, "long-lists")
     g = gpu_run(insts[2].n, insts[2].m, insts[2].d, insts[2].col_idx, insts[2].y, insts[2].alpha)
     assert res[2]["support_size"] == g["support_size"]
+
+
+def test_teams_on_large_instances():
+    """Instances with more than 2^19 column indices are decoded by teams of
+    workgroups (here 14, 6 and the cap of 32, one with bucket words in global
+    memory), mixed with single-workgroup ones; each result against the
+    oracle and against its solo run."""
+    big = [gen.make_instance(41, 1 << 20, 104858, 7, 9000),     # team of 14, words in global memory
+           gen.make_instance(42, 400000, 8000, 7, 1500),        # team of 6, words in LDS
+           gen.make_instance(43, 1 << 22, 41943, 7, 6000),      # team of 32 (cap)
+           gen.make_instance(44, 600000, 60000, 5, 3000)]       # team of 6, words in global memory
+    small = sweep_like(24, 19, n_max_log2=12)
+    insts = big + small
+    say("teams", [(i.n, i.m, i.d) for i in big])
+    res = batched_run(insts, block_threads=512, words_cap=32768)
+    check_all(insts, res, "teams")
+    for q, i in enumerate(big):
+        g = gpu_run(i.n, i.m, i.d, i.col_idx, i.y, i.alpha)
+        assert res[q]["support_size"] == g["support_size"], q
+        assert res[q]["updates"] == g["updates"], q
+
+
+def test_teams_with_small_grid_schedule():
+    """The same large instances with 256-thread workgroups and an 8192-word
+    capacity (more passes, other team sizes)."""
+    insts = [gen.make_instance(45, 1 << 20, 10486, 9, 1000), gen.make_instance(46, 300000, 30000, 5, 2500)]
+    res = batched_run(insts, block_threads=256, words_cap=8192)
+    check_all(insts, res, "teams-256")
