@@ -88,9 +88,12 @@ def main():
     ap.add_argument("--repeats", type=int, default=30, help="l0_solve launches timed for the roofline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--kind", choices=["normal", "pm1"], default="normal")
-    ap.add_argument("--workload", choices=["single", "sweep"], default="single",
+    ap.add_argument("--workload", choices=["single", "sweep", "serve"], default="single",
                     help="single: one n=2^24 instance (default); sweep: 4096 phase-transition "
-                         "instances through the batched decoder")
+                         "instances through the batched decoder; serve: 2000 Poisson-arriving "
+                         "requests through the decoding server")
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: server workspace budget")
     ap.add_argument("--sweep-count", type=int, default=4096)
     ap.add_argument("--autotune", action="store_true", help="sweep: pick the schedule with "
                     "l0_batch_autotune first")
@@ -121,6 +124,8 @@ def main():
         return
     if args.workload == "sweep":
         return sweep(args)
+    if args.workload == "serve":
+        return serve(args)
     kind = gen.VALUES_NORMAL if args.kind == "normal" else gen.VALUES_PM1
     t0 = time.time()
     inst = gen.single_workload("n2^24", 0, kind=kind)
@@ -408,6 +413,133 @@ def sweep(args):
                    "recovered": int(sum(succ)),
                    "outcomes": {l0.OUTCOME_NAMES[k]: int(sum(r["outcome"] == k for r in rl)) for k in (0, 1, 2)},
                    "cells": {k: f"{a}/{b}" for k, (a, b) in sorted(cells.items())}},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve(args):
+    """Serving mix under Poisson arrivals: the decoding server (continuous
+    batching under an HBM budget) against the plain path (one l0_decode_ex
+    per request, in arrival order), at 0.5, 0.9 and 1.5 times the plain
+    path's measured capacity."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1508_01256_amd as l0
+
+    params = gen.serve_params(args.serve_count)
+    t0 = time.time()
+    insts = [gen.make_instance(p["seed"], p["n"], p["m"], p["d"], p["k"], kind=p["kind"]) for p in params]
+    dev = "cuda"
+    reqs = [dict(col=torch.from_numpy(i.col_idx).to(dev), y=torch.from_numpy(i.y).to(dev),
+                 x=torch.empty(i.n, dtype=torch.float64, device=dev), n=i.n, m=i.m, d=i.d, alpha=i.alpha)
+            for i in insts]
+    del insts
+    torch.cuda.synchronize()
+    count = len(reqs)
+    print(f"[bench] generated and uploaded {count} requests in {time.time() - t0:.1f}s "
+          f"(index bytes {sum(4 * r['n'] * r['d'] for r in reqs) / 1e9:.1f} GB)", file=sys.stderr, flush=True)
+
+    # plain path: workspace for the largest request, results as the reference
+    ws = torch.empty(max(l0.l0_workspace_bytes(r["n"], r["m"], r["d"], 100) for r in reqs), dtype=torch.uint8,
+                     device=dev)
+    res1 = l0.new_result(dev)
+
+    def plain_one(r, x):
+        st = l0.l0_decode_ex(r["col"], r["n"], r["m"], r["d"], r["y"], r["alpha"], 100, 1e-10, x, None, res1, ws)
+        assert st == l0.L0_OK, st
+
+    for r in reqs[:20]:
+        plain_one(r, r["x"])
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    for r in reqs:
+        plain_one(r, r["x"])
+    torch.cuda.synchronize()
+    capacity = count / (time.perf_counter() - c0)
+    ref = [r["x"].clone() for r in reqs]
+    print(f"[bench] plain path capacity {capacity:.0f} requests/s", file=sys.stderr, flush=True)
+
+    def pct(v, q):
+        return float(np.percentile(np.asarray(v), q))
+
+    rng = np.random.Generator(np.random.PCG64(gen.SEED + 4500))
+    runs = []
+    for factor in (0.5, 0.9, 1.5):
+        lam = factor * capacity
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, count))
+        # plain path: FIFO, one request at a time, starting when it has arrived
+        lat_plain = []
+        start = time.perf_counter()
+        for r, a in zip(reqs, arrivals):
+            while time.perf_counter() - start < a:
+                pass
+            plain_one(r, r["x"])
+            torch.cuda.synchronize()
+            lat_plain.append(time.perf_counter() - start - a)
+        span_plain = time.perf_counter() - start
+        # server: submit at arrival, poll continuously
+        for r in reqs:
+            r["x"].zero_()
+        torch.cuda.synchronize()
+        srv = l0.Server(int(args.budget_gib * (1 << 30)), max_inflight=4)
+        lat_srv = [None] * count
+        nsub = 0
+        start = time.perf_counter()
+        batches = set()
+        while True:
+            now = time.perf_counter() - start
+            while nsub < count and arrivals[nsub] <= now:
+                r = reqs[nsub]
+                st = srv.submit(nsub, r["col"], r["y"], r["n"], r["m"], r["d"], r["x"], r["alpha"])
+                assert st == l0.L0_OK, st
+                nsub += 1
+            for c in srv.poll():
+                assert c["status"] == l0.L0_OK
+                lat_srv[c["id"]] = time.perf_counter() - start - arrivals[c["id"]]
+                batches.add(c["launch_s"])
+            if nsub == count and srv.outstanding() == 0:
+                break
+        span_srv = time.perf_counter() - start
+        srv.close()
+        same = all(torch.equal(r["x"], x) for r, x in zip(reqs, ref))
+        run = {"load": factor, "lambda_per_s": round(lam, 1),
+               "server": {"p50_ms": round(pct(lat_srv, 50) * 1e3, 3), "p99_ms": round(pct(lat_srv, 99) * 1e3, 3),
+                          "solves_per_s": round(count / span_srv, 1), "batches": len(batches)},
+               "plain": {"p50_ms": round(pct(lat_plain, 50) * 1e3, 3), "p99_ms": round(pct(lat_plain, 99) * 1e3, 3),
+                         "solves_per_s": round(count / span_plain, 1)},
+               "results_equal_solo": same}
+        runs.append(run)
+        print(f"[bench] load {factor}: {json.dumps(run)}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        small = [q for q in range(count) if params[q]["n"] <= (1 << 16)][:40]
+        c0 = time.perf_counter()
+        agree = 0
+        for q in small:
+            i = gen.make_instance(params[q]["seed"], params[q]["n"], params[q]["m"], 7, params[q]["k"],
+                                  kind=params[q]["kind"])
+            o = oracle.parallel_l0(i.n, i.m, i.d, i.col_idx, i.y, i.alpha, max_iter=100, tol=1e-10)
+            agree += int(np.array_equal(o["x"], ref[q].cpu().numpy()))
+        cdt = time.perf_counter() - c0
+        cpu = {"value": round(len(small) / cdt, 2), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(small)} requests with n <= 2^16 (generation included), {cdt:.1f} s single "
+                         f"thread; {agree}/{len(small)} bitwise equal to the GPU results"}
+    top = runs[-1]
+    out = {
+        "metric": "serving: p50/p99 arrival-to-result latency and solves/s under Poisson arrivals",
+        "value": top["server"]["solves_per_s"], "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{count} requests, n=round(2^U) U~U[12,22], delta in {{0.01,0.1}}, d=7, "
+                               "k=floor(0.15m), 10% +-1 nonzeros, Poisson arrivals at 0.5/0.9/1.5 x the plain "
+                               "path's capacity", "budget_gib": args.budget_gib, "max_inflight": 4},
+        "roofline": None,
+        "cpu_baseline": cpu,
+        "detail": {"plain_capacity_per_s": round(capacity, 1), "runs": runs},
     }
     print(json.dumps(out), flush=True)
 

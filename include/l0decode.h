@@ -189,8 +189,8 @@ l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter,
  * the paper's experiments (Section 5).  One persistent launch per range of
  * column degrees present ([2,4], [5,9], [10,14], [15,20]); workgroups take
  * work from a device counter (largest n*d first), a small instance going to
- * one workgroup and a large one to a team of up to 32 that split its columns
- * and rows.  Workspace covers each instance's own scratch.  Each instance's result is
+ * one workgroup and a large one to a team of up to 256 (never more than are
+ * resident) that split its columns and rows.  Workspace covers each instance's own scratch.  Each instance's result is
  * bitwise the one l0_decode_ex gives it alone.  Instances must not share
  * x_out buffers.
  */
@@ -228,7 +228,12 @@ typedef struct {
 size_t l0_batch_workspace_bytes(const l0_problem* probs, int32_t count, const l0_batch_opts* opts);
 
 /*
- * Decode probs[0..count) (host array of device pointers) on `stream`.  results: device l0_result[count] (instance i's at i).
+ * Decode probs[0..count) (host array of device pointers; count < 2^23) on
+ * `stream`.  results: l0_result[count] (instance i's at i) in device memory
+ * or in host memory the device can write (hipHostMalloc): each record's
+ * outcome is written last, after a system-scope fence, so a host that stored
+ * an impossible outcome there first sees each instance complete, x_out
+ * included, as soon as it is.
  * Workspace: device memory of at least l0_batch_workspace_bytes, 256-byte
  * aligned, caller-owned.  Every instance is validated on the host first
  * (L0_ERR_ARG names no instance; check them individually to find it).
@@ -248,6 +253,60 @@ l0_status l0_decode_batched(const l0_problem* probs, int32_t count, const l0_bat
  */
 l0_status l0_batch_autotune(const l0_problem* probs, int32_t count, l0_batch_opts* opts,
                             l0_result* results, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Serving: a decoding server that accepts requests one at a time and decodes
+ * them in batches (l0_decode_batched) under a fixed device-memory budget, as
+ * a service answering many independent decoding requests would.  Requests
+ * waiting when a batch slot is free go into the next batch (first come,
+ * first served, as many as fit the free budget); up to max_inflight batches
+ * run at once, each on a stream of the server's own.  A request's buffers
+ * (col_idx, y, x_out) are the caller's and must stay valid until its
+ * completion is returned.  Calls on one server are serialised by a lock;
+ * the server uses the device that is current when it is created.
+ */
+typedef struct l0_server_s* l0_server;
+
+typedef struct {
+    size_t budget_bytes;   /* device memory for batch workspaces (allocated at creation) */
+    int32_t max_batch;     /* most requests in one batch (0: 1024) */
+    int32_t max_inflight;  /* batches running at once, 1..4 (0: 2) */
+    l0_batch_opts batch;   /* rule, tol_mode and schedule of every batch (timing must be NULL) */
+} l0_server_opts;
+
+typedef struct {
+    int64_t id;            /* the caller's request id */
+    int32_t status;        /* L0_OK, or the l0_status that failed the request's batch */
+    int32_t reserved;
+    l0_result result;      /* outcome of the decode (valid when status is L0_OK) */
+    double submit_s;       /* server clock (seconds since creation): submission */
+    double launch_s;       /* its batch was launched */
+    double done_s;         /* the server saw the batch finish (poll or drain) */
+} l0_completion;
+
+/* Create a server; L0_ERR_ARG on invalid options, L0_ERR_OOM if the budget
+ * cannot be allocated. */
+l0_status l0_server_create(const l0_server_opts* opts, l0_server* out);
+
+/* Queue one request (the record is copied).  L0_ERR_ARG on an invalid
+ * problem or buffer, L0_ERR_WORKSPACE when it alone needs more than the
+ * budget.  Does not launch anything: l0_server_poll does. */
+l0_status l0_server_submit(l0_server s, const l0_problem* prob, int64_t id);
+
+/* Make progress without blocking: collect finished batches, launch new ones
+ * from the waiting requests, and copy up to cap completions (oldest first)
+ * to out.  Returns the number copied, or minus an l0_status on failure. */
+int32_t l0_server_poll(l0_server s, l0_completion* out, int32_t cap);
+
+/* Block until every submitted request has completed (launching batches as
+ * slots free up); completions stay queued for l0_server_poll. */
+l0_status l0_server_drain(l0_server s);
+
+/* Requests submitted whose completion has not yet been returned by poll. */
+int64_t l0_server_outstanding(l0_server s);
+
+/* Wait for running batches, free the server.  NULL is accepted. */
+l0_status l0_server_destroy(l0_server s);
 
 #ifdef __cplusplus
 }

@@ -36,7 +36,9 @@ L0_TOL_RELATIVE, L0_TOL_ABSOLUTE = 0, 1
 #: every entry point declared in include/l0decode.h
 EXPORTED = ("l0_version", "l0_status_string", "l0_decode", "l0_workspace_bytes", "l0_decode_ex",
             "l0_matrix_create", "l0_matrix_destroy", "l0_solve_workspace_bytes", "l0_solve",
-            "l0_batch_workspace_bytes", "l0_decode_batched", "l0_batch_autotune")
+            "l0_batch_workspace_bytes", "l0_decode_batched", "l0_batch_autotune",
+            "l0_server_create", "l0_server_submit", "l0_server_poll", "l0_server_drain",
+            "l0_server_outstanding", "l0_server_destroy")
 
 
 class LibraryMissing(RuntimeError):
@@ -69,6 +71,23 @@ class l0_batch_opts(ctypes.Structure):
                 ("timing", ctypes.c_void_p)]
 
 
+class l0_result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outcome", ctypes.c_int32),
+                ("final_nnz", ctypes.c_int32), ("support_size", ctypes.c_int32),
+                ("updates", ctypes.c_int64)]
+
+
+class l0_server_opts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("batch", l0_batch_opts)]
+
+
+class l0_completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("result", l0_result), ("submit_s", ctypes.c_double), ("launch_s", ctypes.c_double),
+                ("done_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -95,8 +114,15 @@ def lib():
         L.l0_batch_workspace_bytes.restype = SZ
         L.l0_decode_batched.argtypes = [P, I32, P, P, P, SZ, P]
         L.l0_batch_autotune.argtypes = [P, I32, P, P, P, SZ, P]
+        L.l0_server_create.argtypes = [P, ctypes.POINTER(P)]
+        L.l0_server_submit.argtypes = [P, P, I64]
+        L.l0_server_poll.argtypes, L.l0_server_poll.restype = [P, P, I32], I32
+        L.l0_server_drain.argtypes = [P]
+        L.l0_server_outstanding.argtypes, L.l0_server_outstanding.restype = [P], I64
+        L.l0_server_destroy.argtypes = [P]
         for f in ("l0_decode", "l0_decode_ex", "l0_matrix_create", "l0_matrix_destroy", "l0_solve",
-                  "l0_decode_batched", "l0_batch_autotune"):
+                  "l0_decode_batched", "l0_batch_autotune", "l0_server_create", "l0_server_submit",
+                  "l0_server_drain", "l0_server_destroy"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -198,6 +224,32 @@ def l0_batch_autotune(table, opts, results, workspace) -> int:
                                    _stream())
 
 
+def l0_server_create(opts):
+    h = ctypes.c_void_p()
+    st = lib().l0_server_create(ctypes.byref(opts), ctypes.byref(h))
+    return st, h
+
+
+def l0_server_submit(h, problem, req_id) -> int:
+    return lib().l0_server_submit(h, ctypes.byref(problem), int(req_id))
+
+
+def l0_server_poll(h, out, cap) -> int:
+    return lib().l0_server_poll(h, out, cap)
+
+
+def l0_server_drain(h) -> int:
+    return lib().l0_server_drain(h)
+
+
+def l0_server_outstanding(h) -> int:
+    return lib().l0_server_outstanding(h)
+
+
+def l0_server_destroy(h) -> int:
+    return lib().l0_server_destroy(h)
+
+
 # ---------------------------------------------------------------------------
 # conveniences
 # ---------------------------------------------------------------------------
@@ -276,6 +328,69 @@ def decode_batched(problems, *, rule=L0_RULE_L0DEC, tol_mode=L0_TOL_RELATIVE, bl
     _check(l0_decode_batched(table, opts, results, ws), "l0_decode_batched")
     torch.cuda.current_stream().synchronize()
     return [q["x_out"] for q in full], results_list(results)
+
+
+def _completion_dict(c):
+    r = c.result
+    return dict(id=c.id, status=c.status, iters=r.iters, outcome=r.outcome, final_nnz=r.final_nnz,
+                support_size=r.support_size, updates=r.updates, submit_s=c.submit_s,
+                launch_s=c.launch_s, done_s=c.done_s)
+
+
+class Server:
+    """A decoding server (l0_server_*): submit() queues a request, poll()
+    makes progress and returns finished ones, drain() waits for all.  The
+    request's tensors are kept referenced until its completion is returned."""
+
+    def __init__(self, budget_bytes, *, max_batch=0, max_inflight=0, rule=L0_RULE_L0DEC,
+                 tol_mode=L0_TOL_RELATIVE, block_threads=0, words_cap=0):
+        self.opts = l0_server_opts(budget_bytes, max_batch, max_inflight,
+                                   l0_batch_opts(rule, tol_mode, block_threads, words_cap, None))
+        st, h = l0_server_create(self.opts)
+        _check(st, "l0_server_create")
+        self.handle = h
+        self._keep = {}
+        self._buf = (l0_completion * 256)()
+
+    def submit(self, req_id, col_idx, y, n, m, d, x_out, alpha=None, max_iter=100, tol=1e-10):
+        alpha = float(max(math.ceil(d / 2), 2)) if alpha is None else float(alpha)
+        prob = l0_problem(col_idx.data_ptr(), n, m, d, y.data_ptr(), alpha, max_iter, 0, float(tol),
+                          x_out.data_ptr())
+        st = l0_server_submit(self.handle, prob, req_id)
+        if st == L0_OK:
+            self._keep[int(req_id)] = (col_idx, y, x_out)
+        return st
+
+    def poll(self):
+        out = []
+        while True:
+            k = l0_server_poll(self.handle, self._buf, len(self._buf))
+            if k < 0:
+                raise L0Error(-k, "l0_server_poll")
+            for c in self._buf[:k]:
+                self._keep.pop(int(c.id), None)
+                out.append(_completion_dict(c))
+            if k < len(self._buf):
+                return out
+
+    def drain(self):
+        _check(l0_server_drain(self.handle), "l0_server_drain")
+        return self.poll()
+
+    def outstanding(self):
+        return l0_server_outstanding(self.handle)
+
+    def close(self):
+        if self.handle:
+            _check(l0_server_destroy(self.handle), "l0_server_destroy")
+            self.handle = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Matrix:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libl0decode.so")
-SOURCES = ["l0_kernels.hip", "l0_batch.hip", "l0_api.hip"]
+SOURCES = ["l0_kernels.hip", "l0_batch.hip", "l0_api.hip", "l0_server.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

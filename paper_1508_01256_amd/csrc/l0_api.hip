@@ -186,6 +186,12 @@ bool common_buffers_ok(int64_t n, int32_t m, int32_t max_iter, const double* y, 
 
 }  // namespace
 
+namespace l0 {
+
+bool device_buffer_ok(const void* p, size_t bytes) { return buffer_ok(p, bytes); }
+
+}  // namespace l0
+
 extern "C" {
 
 const char* l0_version(void) { return "l0decode 0.1 (gfx950)"; }

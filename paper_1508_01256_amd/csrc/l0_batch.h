@@ -66,9 +66,9 @@ struct alignas(256) TeamCtl {
     IterCounters ring[3];
 };
 
-// Work items: instance index in the low 24 bits, team member in the high 7.
-constexpr int kItemInstBits = 24;
-constexpr int kMaxTeam = 32;
+// Work items: instance index in the low 23 bits, team member in the high 8.
+constexpr int kItemInstBits = 23;
+constexpr int kMaxTeam = 256;
 
 struct BatchParams {
     const l0_problem* probs;  // device copy of the instance table

@@ -409,13 +409,17 @@ __device__ double long_row_residual(const BlockState& s, const Lds& L, int i) {
     return s.y[i] - sum;
 }
 
+// The outcome is written last, after a system-scope fence: a host polling
+// results in host-mapped memory sees a complete record (and a finished
+// x_hat) once the outcome is no longer the value it stored there.
 __device__ void write_result(gptr<l0_result> res, int iters, int outcome, int nnz, int support,
                              long long updates) {
     res->iters = iters;
-    res->outcome = outcome;
     res->final_nnz = nnz;
     res->support_size = support;
     res->updates = updates;
+    __threadfence_system();
+    __hip_atomic_store(&res->outcome, outcome, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Device clock (constant 100 MHz), read by thread 0 for the optional

@@ -125,4 +125,7 @@ int device_cus();
 // Bound of one device-side wait (20 s) in ticks of the device's constant clock.
 uint64_t wait_limit_ticks();
 
+// A device-accessible buffer of at least `bytes` at p (the C-ABI's check).
+bool device_buffer_ok(const void* p, size_t bytes);
+
 }  // namespace l0

@@ -146,6 +146,10 @@ def test_struct_layouts_match_the_header(tmp_path):
         '  F(l0_problem, max_iter) F(l0_problem, tol) F(l0_problem, x_out)\n'
         '  F(l0_opts, x_init) F(l0_opts, timeline) F(l0_batch_opts, words_cap)\n'
         '  F(l0_batch_opts, timing)\n'
+        '  printf("l0_server_opts %zu\\n", sizeof(l0_server_opts));\n'
+        '  printf("l0_completion %zu\\n", sizeof(l0_completion));\n'
+        '  F(l0_server_opts, batch) F(l0_completion, result) F(l0_completion, submit_s)\n'
+        '  F(l0_completion, done_s)\n'
         '  F(l0_result, updates)\n'
         '  return 0;\n}\n')
     exe = tmp_path / "layout"
@@ -163,10 +167,34 @@ def test_struct_layouts_match_the_header(tmp_path):
     assert got["l0_problem"] == ctypes.sizeof(l0.l0_problem)
     assert got["l0_batch_opts"] == ctypes.sizeof(l0.l0_batch_opts)
     assert got["l0_result"] == 24  # the binding's int64[3] result records
+    assert got["l0_server_opts"] == ctypes.sizeof(l0.l0_server_opts)
+    assert got["l0_completion"] == ctypes.sizeof(l0.l0_completion)
+    assert got["l0_result"] == ctypes.sizeof(l0.l0_result)
     for name, cls in [("l0_problem", l0.l0_problem), ("l0_opts", l0.l0_opts),
-                      ("l0_batch_opts", l0.l0_batch_opts)]:
+                      ("l0_batch_opts", l0.l0_batch_opts), ("l0_server_opts", l0.l0_server_opts),
+                      ("l0_completion", l0.l0_completion)]:
         for f, _ in cls._fields_:
             key = f"{name}.{f}"
             if key in got:
                 assert got[key] == getattr(cls, f).offset, key
     assert got["l0_result.updates"] == 16
+
+
+def test_server_argument_errors():
+    L = l0.lib()
+    h = ctypes.c_void_p()
+    assert L.l0_server_create(None, ctypes.byref(h)) == l0.L0_ERR_ARG
+    for o in [l0.l0_server_opts(0, 0, 0, l0.l0_batch_opts()),
+              l0.l0_server_opts(1 << 20, -1, 0, l0.l0_batch_opts()),
+              l0.l0_server_opts(1 << 20, 0, 5, l0.l0_batch_opts()),
+              l0.l0_server_opts(1 << 20, 0, 0, l0.l0_batch_opts(rule=3)),
+              l0.l0_server_opts(1 << 20, 0, 0, l0.l0_batch_opts(block_threads=1024)),
+              l0.l0_server_opts(1 << 20, 0, 0, l0.l0_batch_opts(timing=1))]:
+        assert L.l0_server_create(ctypes.byref(o), ctypes.byref(h)) == l0.L0_ERR_ARG
+    o = l0.l0_server_opts(1 << 20, 0, 0, l0.l0_batch_opts())
+    assert L.l0_server_create(ctypes.byref(o), None) == l0.L0_ERR_ARG
+    assert L.l0_server_submit(None, None, 0) == l0.L0_ERR_ARG
+    assert L.l0_server_poll(None, None, 0) == -l0.L0_ERR_ARG
+    assert L.l0_server_drain(None) == l0.L0_ERR_ARG
+    assert L.l0_server_outstanding(None) == 0
+    assert L.l0_server_destroy(None) == l0.L0_OK
