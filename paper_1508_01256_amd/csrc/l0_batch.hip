@@ -627,7 +627,7 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
             const int i = s.aff_list[q];
             const int cnt = s.slot_cnt[i];
             if (cnt <= kShortList) {
-                delta += finish_row(s, L, wl, i, row_residual_short(s, i, cnt), tau, inv_w);
+                delta += finish_row(s, L, wl, i, row_residual_any(s, i, cnt), tau, inv_w);
             } else {
                 const int k = fetch_add(&L.ctr[0], 1);
                 if (k < long_cap) long_rows[k] = i;

@@ -97,31 +97,42 @@ __device__ __forceinline__ void sort_network(int (&v)[N]) {
     }
 }
 
-// row_residual for a row whose support list holds cnt <= kShortList
-// entries: the list is sorted in registers (and written back) when it has
-// unsorted entries, x_hat is gathered for all entries at once, and the sum
-// still runs in ascending j from +0.0.
-template <class S>
+// row_residual for a row whose support list holds cnt <= N entries (N a
+// power of two): the list is sorted in registers (and written back) when it
+// has unsorted entries, x_hat is gathered for all entries at once, and the
+// sum still runs in ascending j from +0.0.
+template <int N, class S>
 __device__ double row_residual_short(const S& p, int i, int cnt) {
     const auto list = p.slots + p.row_off[i];
-    int v[kShortList];
+    int v[N];
 #pragma unroll
-    for (int q = 0; q < kShortList; ++q) v[q] = q < cnt ? list[q] : INT_MAX;
+    for (int q = 0; q < N; ++q) v[q] = q < cnt ? list[q] : INT_MAX;
     if (p.slot_sorted[i] != cnt) {
-        sort_network<kShortList>(v);
+        sort_network<N>(v);
 #pragma unroll
-        for (int q = 0; q < kShortList; ++q)
+        for (int q = 0; q < N; ++q)
             if (q < cnt) list[q] = v[q];
         p.slot_sorted[i] = cnt;
     }
-    double xv[kShortList];
+    double xv[N];
 #pragma unroll
-    for (int q = 0; q < kShortList; ++q) xv[q] = q < cnt ? p.x[v[q]] : 0.0;
+    for (int q = 0; q < N; ++q) xv[q] = q < cnt ? p.x[v[q]] : 0.0;
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < kShortList; ++q)
+    for (int q = 0; q < N; ++q)
         if (q < cnt) s += xv[q];
     return p.y[i] - s;
+}
+
+// row_residual by list length: the plain merge for one or two entries
+// (nothing to gain), register networks of 4, 8 or 16 entries, the plain
+// merge again above kShortList.
+template <class S>
+__device__ double row_residual_any(const S& p, int i, int cnt) {
+    if (cnt <= 2 || cnt > kShortList) return row_residual(p, i);
+    if (cnt <= 4) return row_residual_short<4>(p, i, cnt);
+    if (cnt <= 8) return row_residual_short<8>(p, i, cnt);
+    return row_residual_short<16>(p, i, cnt);
 }
 
 }  // namespace l0
