@@ -21,6 +21,8 @@ _LIB = os.path.join(_HERE, "libl0oracle.so")
 
 RULE_L0DEC = 0
 RULE_MODE = 1
+RULE_SHIFTED_L0DEC = 2  # Algorithm 3: one candidate per column per pass
+RULE_SHIFTED_MODE = 3
 CONVERGED, STALLED, MAX_ITER = 0, 1, 2
 OUTCOME_NAMES = {CONVERGED: "CONVERGED", STALLED: "STALLED", MAX_ITER: "MAX_ITER"}
 
@@ -45,7 +47,7 @@ def _load():
             build(force=False)
         lib = ctypes.CDLL(_LIB)
         P, I32, I64, F64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-        lib.orc_parallel_l0.argtypes = [I64, I32, I32, P, P, F64, I32, I32, F64, P, P, P, P, P, P]
+        lib.orc_parallel_l0.argtypes = [I64, I32, I32, P, P, F64, I32, I32, F64, P, P, P, P, P, P, P]
         lib.orc_parallel_l0.restype = ctypes.c_int
         lib.orc_serial_l0.argtypes = [I64, I32, I32, P, P, F64, I32, I32, F64, P, P, P, P, P]
         lib.orc_serial_l0.restype = ctypes.c_int
@@ -53,6 +55,8 @@ def _load():
         lib.orc_residual.restype = None
         lib.orc_score_columns.argtypes = [I64, I32, P, P, F64, I32, I32, P, P, P]
         lib.orc_score_columns.restype = None
+        lib.orc_score_columns_shifted.argtypes = [I64, I32, P, P, F64, I32, I32, I32, P, P]
+        lib.orc_score_columns_shifted.restype = None
         lib.orc_literal_decrease.argtypes = [I32, I32, P, P, F64, F64]
         lib.orc_literal_decrease.restype = I32
         _lib = lib
@@ -69,21 +73,23 @@ def _c(a, dt):
 
 def parallel_l0(n, m, d, col_idx, y, alpha, *, max_iter=100, tol=1e-10, rule=RULE_L0DEC,
                 x_init=None):
-    """Run Parallel-l0; returns dict(x, iters, outcome, trace, tsize)."""
+    """Run Parallel-l0 (rules L0DEC, MODE) or its shifted form (Algorithm 3;
+    rules SHIFTED_L0DEC, SHIFTED_MODE); returns dict(x, iters, outcome, trace,
+    tsize, passes) where passes counts vote passes."""
     col_idx, y = _c(col_idx, np.int32), _c(y, np.float64)
     xi = None if x_init is None else _c(x_init, np.float64)
     x = np.empty(n, dtype=np.float64)
     trace = np.zeros(max_iter + 1, dtype=np.int32)
     tsize = np.zeros(max(max_iter, 1), dtype=np.int64)
-    iters, outcome = ctypes.c_int32(), ctypes.c_int32()
+    iters, outcome, passes = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     rc = _load().orc_parallel_l0(n, m, d, _p(col_idx), _p(y), float(alpha), rule, max_iter,
                                  float(tol), _p(xi), _p(x), _p(trace), _p(tsize),
-                                 ctypes.byref(iters), ctypes.byref(outcome))
+                                 ctypes.byref(iters), ctypes.byref(outcome), ctypes.byref(passes))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     it = iters.value
     return dict(x=x, iters=it, outcome=outcome.value, trace=trace[: it + 1].copy(),
-                tsize=tsize[:it].copy())
+                tsize=tsize[:it].copy(), passes=passes.value)
 
 
 def serial_l0(n, m, d, col_idx, y, alpha, *, max_sweeps=100, tol=1e-10, rule=RULE_L0DEC):
@@ -121,6 +127,19 @@ def score_columns(rows, d, r, tau, a, rule=RULE_L0DEC):
         _load().orc_score_columns(nc, d, _p(rows), _p(r), float(tau), rule, int(a), _p(sel),
                                   _p(omega), _p(best))
     return sel, omega, best
+
+
+def score_columns_shifted(rows, d, r, tau, a, t, rule=RULE_SHIFTED_L0DEC):
+    """One shifted vote: each column tries only the value of r at its t-th
+    neighbour.  Returns (sel uint8, omega float64) per column."""
+    rows, r = _c(rows, np.int32), _c(r, np.float64)
+    nc = rows.size // d
+    sel = np.zeros(nc, dtype=np.uint8)
+    omega = np.zeros(nc, dtype=np.float64)
+    if nc:
+        _load().orc_score_columns_shifted(nc, d, _p(rows), _p(r), float(tau), rule, int(a), int(t),
+                                          _p(sel), _p(omega))
+    return sel, omega
 
 
 def literal_decrease(rows, r, omega, tau):

@@ -29,6 +29,15 @@
  *    updates (Definition 3.1).
  * Rule MODE scores a candidate by its frequency in r_N(j) instead of the
  * l0-decrease (parallel-LDDSR, Section 4.3 and Table 2).
+ *
+ * Shifted rules (Section 4.3.1, Algorithm 3 and Theorem 4.8): at the p-th
+ * vote pass (p = 0, 1, ...) column j tries one candidate only, the value of r
+ * at its (p mod d)-th neighbour in col_idx order, scored by the l0-decrease
+ * (SHIFTED_L0DEC) or its frequency (SHIFTED_MODE); a zero candidate is not
+ * tried.  A pass that selects nothing leaves r as it is but the next pass
+ * tries other positions, so the run stalls only after d consecutive empty
+ * passes.  Readings: p counts vote passes, not residual updates; "the
+ * (p mod d)-th element of r_N(j)" is taken in col_idx order.
  */
 #include <limits.h>
 #include <math.h>
@@ -36,7 +45,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_RULE_L0DEC = 0, ORC_RULE_MODE = 1 };
+enum { ORC_RULE_L0DEC = 0, ORC_RULE_MODE = 1, ORC_RULE_SHIFTED_L0DEC = 2, ORC_RULE_SHIFTED_MODE = 3 };
 enum { ORC_CONVERGED = 0, ORC_STALLED = 1, ORC_MAX_ITER = 2 };
 
 static int is_nonzero(double v, double tau) { return fabs(v) > tau; }
@@ -73,11 +82,33 @@ static int score_column(int32_t d, const double* v, double tau, int32_t rule, in
     return top != INT_MIN && top >= a;
 }
 
+/*
+ * Shifted score of one column: the only candidate is omega = v[t]; it is
+ * tried when nonzero, scored as in score_column, and selected when the score
+ * reaches a.
+ */
+static int score_column_shifted(int32_t d, const double* v, int32_t t, double tau, int32_t shifted_rule,
+                                int32_t a, double* omega) {
+    *omega = 0.0;
+    if (!is_nonzero(v[t], tau)) return 0;
+    int32_t before = 0, after = 0, freq = 0;
+    for (int32_t u = 0; u < d; ++u) {
+        before += is_nonzero(v[u], tau);
+        double diff = v[u] - v[t];
+        after += is_nonzero(diff, tau);
+        freq += !is_nonzero(diff, tau);
+    }
+    int32_t score = (shifted_rule == ORC_RULE_SHIFTED_MODE) ? freq : before - after;
+    if (score < a) return 0;
+    *omega = v[t];
+    return 1;
+}
+
 static int args_ok(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const double* y,
                    double alpha, int32_t rule, int32_t max_iter, double tol) {
     if (n < 1 || m < 1 || d < 2 || d > m || !col_idx || !y) return 0;
     if (!(alpha > 1.0) || !(alpha <= (double)d)) return 0;
-    if (rule != ORC_RULE_L0DEC && rule != ORC_RULE_MODE) return 0;
+    if (rule < ORC_RULE_L0DEC || rule > ORC_RULE_SHIFTED_MODE) return 0;
     if (max_iter < 0 || !(tol >= 0.0) || !isfinite(tol)) return 0;
     for (int64_t e = 0; e < n * (int64_t)d; ++e)
         if (col_idx[e] < 0 || col_idx[e] >= m) return 0;
@@ -125,6 +156,17 @@ void orc_score_columns(int64_t ncols, int32_t d, const int32_t* rows, const doub
     free(v);
 }
 
+/* The shifted vote of one pass: column c tries position t only. */
+void orc_score_columns_shifted(int64_t ncols, int32_t d, const int32_t* rows, const double* r, double tau,
+                               int32_t shifted_rule, int32_t a, int32_t t, uint8_t* sel, double* omega) {
+    double* v = (double*)malloc(sizeof(double) * (size_t)d);
+    for (int64_t c = 0; c < ncols; ++c) {
+        for (int32_t u = 0; u < d; ++u) v[u] = r[rows[c * d + u]];
+        sel[c] = (uint8_t)score_column_shifted(d, v, t, tau, shifted_rule, a, &omega[c]);
+    }
+    free(v);
+}
+
 /*
  * ||r||_0 - ||r - omega a_j||_0 over the whole m-vector, forming r - omega a_j
  * entry by entry (the definition in eq. (selection_l0), used as a pin).
@@ -149,7 +191,7 @@ int32_t orc_literal_decrease(int32_t m, int32_t d, const int32_t* rows, const do
 int orc_parallel_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const double* y,
                     double alpha, int32_t rule, int32_t max_iter, double tol, const double* x_init,
                     double* x_out, int32_t* trace, int64_t* tsize, int32_t* iters,
-                    int32_t* outcome) {
+                    int32_t* outcome, int32_t* passes) {
     if (!args_ok(n, m, d, col_idx, y, alpha, rule, max_iter, tol) || !x_out || !trace || !iters ||
         !outcome)
         return -1;
@@ -162,7 +204,8 @@ int orc_parallel_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, con
 
     for (int64_t j = 0; j < n; ++j) x_out[j] = x_init ? x_init[j] : 0.0;
     orc_residual(n, m, d, col_idx, y, x_out, r);
-    int32_t l = 0;
+    const int shifted = rule == ORC_RULE_SHIFTED_L0DEC || rule == ORC_RULE_SHIFTED_MODE;
+    int32_t l = 0, p = 0, empty = 0;
     trace[0] = count_nonzero(m, r, tau);
     for (;;) {
         if (trace[l] == 0) { *outcome = ORC_CONVERGED; break; }
@@ -172,10 +215,20 @@ int orc_parallel_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, con
         for (int64_t j = 0; j < n; ++j) {
             int32_t best;
             for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d + t]];
-            sel[j] = (uint8_t)score_column(d, v, tau, rule, a, &omega[j], &best);
+            if (shifted)
+                sel[j] = (uint8_t)score_column_shifted(d, v, p % d, tau, rule, a, &omega[j]);
+            else
+                sel[j] = (uint8_t)score_column(d, v, tau, rule, a, &omega[j], &best);
             chosen += sel[j];
         }
-        if (chosen == 0) { *outcome = ORC_STALLED; break; }
+        ++p;
+        if (chosen == 0) {
+            /* shifted: r is unchanged, but the next pass tries the next position */
+            if (shifted && ++empty < d) continue;
+            *outcome = ORC_STALLED;
+            break;
+        }
+        empty = 0;
         for (int64_t j = 0; j < n; ++j)
             if (sel[j]) x_out[j] = x_out[j] + omega[j];
         orc_residual(n, m, d, col_idx, y, x_out, r);
@@ -184,6 +237,7 @@ int orc_parallel_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, con
         trace[l] = count_nonzero(m, r, tau);
     }
     *iters = l;
+    if (passes) *passes = p;
     free(r); free(v); free(omega); free(sel);
     return 0;
 }
@@ -202,7 +256,7 @@ int orc_serial_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const
                   double alpha, int32_t rule, int32_t max_sweeps, double tol, double* x_out,
                   int64_t* updates, int32_t* sweeps, int32_t* outcome, int32_t* final_nnz) {
     if (!args_ok(n, m, d, col_idx, y, alpha, rule, max_sweeps, tol) || !x_out || !updates ||
-        !sweeps || !outcome)
+        !sweeps || !outcome || rule > ORC_RULE_MODE)
         return -1;
     const int32_t a = (int32_t)ceil(alpha);
     const double tau = zero_threshold(m, y, tol);

@@ -12,7 +12,8 @@ import oracle
 from golden_io import decode_cases, graph_arrays, load, num
 from oracle import brute
 
-RULES = {"L0DEC": oracle.RULE_L0DEC, "MODE": oracle.RULE_MODE}
+RULES = {"L0DEC": oracle.RULE_L0DEC, "MODE": oracle.RULE_MODE, "SHIFTED_L0DEC": oracle.RULE_SHIFTED_L0DEC,
+         "SHIFTED_MODE": oracle.RULE_SHIFTED_MODE}
 OUT = {"CONVERGED": oracle.CONVERGED, "STALLED": oracle.STALLED, "MAX_ITER": oracle.MAX_ITER}
 
 
@@ -45,6 +46,8 @@ def test_worked_decodes(case):
         assert res["trace"].tolist() == c["trace"]
         assert res["tsize"].tolist() == c["tsize"]
         assert res["iters"] == c["iters"]
+        if "passes" in c:
+            assert res["passes"] == c["passes"]
     else:
         res = oracle.serial_l0(n, m, d, col, y, c["alpha"], max_sweeps=c["max_iter"], tol=c["tol"],
                                rule=RULES[c["rule"]])

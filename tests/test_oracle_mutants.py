@@ -11,23 +11,30 @@ import pytest
 
 import oracle
 import test_oracle as pins
+import test_oracle_shifted as spins
 from golden_io import decode_cases
 
 MUTANTS = {
     "residual_sign": ("r[i] = y[i] - s[i];", "r[i] = y[i] + s[i];"),
     "update_sign": ("x_out[j] = x_out[j] + omega[j];", "x_out[j] = x_out[j] - omega[j];"),
     "tie_break_largest": ("(score == top && v[t] < w)", "(score == top && v[t] > w)"),
-    "drop_zero_count": ("? freq : before - after;", "? freq : d - after;"),
+    "drop_zero_count": ("(rule == ORC_RULE_MODE) ? freq : before - after;", "(rule == ORC_RULE_MODE) ? freq : d - after;"),
+    "shift_drop_zero_count": ("(shifted_rule == ORC_RULE_SHIFTED_MODE) ? freq : before - after;",
+                              "(shifted_rule == ORC_RULE_SHIFTED_MODE) ? freq : d - after;"),
     "threshold_floor": ("const int32_t a = (int32_t)ceil(alpha);\n    const double tau = zero_threshold(m, y, tol);\n    double* r",
                         "const int32_t a = (int32_t)floor(alpha);\n    const double tau = zero_threshold(m, y, tol);\n    double* r"),
     "strict_threshold": ("return top != INT_MIN && top >= a;", "return top != INT_MIN && top > a;"),
     "zero_test_nonstrict": ("return fabs(v) > tau;", "return fabs(v) >= tau;"),
-    "gather_index": ("for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d + t]];\n            sel[j]",
-                     "for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d]];\n            sel[j]"),
+    "gather_index": ("for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d + t]];\n            if (shifted)",
+                     "for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d]];\n            if (shifted)"),
     "residual_skips_last_row": ("for (int32_t i = 0; i < m; ++i) r[i] = y[i] - s[i];",
                                 "for (int32_t i = 0; i + 1 < m; ++i) r[i] = y[i] - s[i];"),
     "serial_row_recompute_missing": ("r[i] = y[i] - s;", "r[i] = y[i] - s * (t == 0);"),
     "tau_absolute": ("return tol * s;", "return tol;"),
+    "shift_offset": ("score_column_shifted(d, v, p % d,", "score_column_shifted(d, v, (p + 1) % d,"),
+    "shift_position_by_update": ("score_column_shifted(d, v, p % d,", "score_column_shifted(d, v, l % d,"),
+    "shift_no_retry": ("if (shifted && ++empty < d) continue;", "if (shifted && ++empty < 1) continue;"),
+    "shift_zero_candidate": ("    *omega = 0.0;\n    if (!is_nonzero(v[t], tau)) return 0;\n", "    *omega = 0.0;\n"),
 }
 
 
@@ -46,6 +53,11 @@ def _run_pins():
         ("true_updates", lambda: pins.test_updates_are_true_values_and_trace_decreases(0)),
         ("scaling", lambda: [pins.test_power_of_two_scaling_bitwise(e) for e in (-40, 5)]),
         ("serial_parallel", pins.test_serial_and_parallel_agree),
+        ("shift_literal", lambda: [spins.test_shifted_selection_is_the_literal_score_of_one_candidate(t, r)
+                                   for t in (0.0, 1e-9) for r in (oracle.RULE_L0DEC, oracle.RULE_MODE)]),
+        ("shift_subset", spins.test_shifted_selects_a_subset_of_the_full_vote),
+        ("shift_closed", spins.test_shifted_k0_and_disjoint_columns),
+        ("shift_theorem", lambda: spins.test_theorem_4_8_on_dissociated_signals(0)),
     ]
     for name, fn in checks:
         try:
