@@ -70,7 +70,15 @@ typedef enum {
 
 typedef enum {
     L0_RULE_L0DEC = 0, /* score = l0-decrease ||r||_0 - ||r - omega a_j||_0 (Algorithm 2) */
-    L0_RULE_MODE = 1   /* score = frequency of omega in r_N(j) (parallel-LDDSR, Table 2) */
+    L0_RULE_MODE = 1,  /* score = frequency of omega in r_N(j) (parallel-LDDSR, Table 2) */
+    /* Shifted Parallel-l0 (Section 4.3.1, Algorithm 3, Theorem 4.8): at vote
+     * pass p every column tries one candidate only, the value of r at its
+     * (p mod d)-th neighbour in col_idx order (not tried when zero), scored as
+     * L0DEC or MODE.  A pass selecting nothing leaves r unchanged and the next
+     * pass tries the next position; d such passes in a row end the run as
+     * L0_STALLED.  iters, trace and |T| count residual updates as before. */
+    L0_RULE_SHIFTED_L0DEC = 2,
+    L0_RULE_SHIFTED_MODE = 3
 } l0_rule;
 
 typedef enum {

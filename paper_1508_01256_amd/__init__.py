@@ -30,7 +30,7 @@ L0_DEV_BAD_INDEX, L0_DEV_NONFINITE_Y, L0_DEV_ABORTED = 16, 17, 19
 OUTCOME_NAMES = {0: "CONVERGED", 1: "STALLED", 2: "MAX_ITER", 16: "DEV_BAD_INDEX",
                  17: "DEV_NONFINITE_Y", 19: "DEV_ABORTED"}
 # rules and tolerance modes
-L0_RULE_L0DEC, L0_RULE_MODE = 0, 1
+L0_RULE_L0DEC, L0_RULE_MODE, L0_RULE_SHIFTED_L0DEC, L0_RULE_SHIFTED_MODE = 0, 1, 2, 3
 L0_TOL_RELATIVE, L0_TOL_ABSOLUTE = 0, 1
 
 #: every entry point declared in include/l0decode.h

@@ -64,7 +64,7 @@ bool solve_args_ok(double alpha, int32_t d, int32_t max_iter, double tol) {
 
 bool opts_ok(const l0_opts* o) {
     if (!o) return true;
-    if (o->rule != L0_RULE_L0DEC && o->rule != L0_RULE_MODE) return false;
+    if ((o->rule < L0_RULE_L0DEC || o->rule > L0_RULE_SHIFTED_MODE)) return false;
     if (o->tol_mode != L0_TOL_RELATIVE && o->tol_mode != L0_TOL_ABSOLUTE) return false;
     return o->reserved0 == 0 && o->reserved1 == 0;
 }
@@ -360,7 +360,7 @@ constexpr int64_t kTeamUnit = int64_t(1) << 19;  // estimated cost per team memb
 
 bool batch_opts_ok(const l0_batch_opts* o) {
     if (!o) return true;
-    if (o->rule != L0_RULE_L0DEC && o->rule != L0_RULE_MODE) return false;
+    if ((o->rule < L0_RULE_L0DEC || o->rule > L0_RULE_SHIFTED_MODE)) return false;
     if (o->tol_mode != L0_TOL_RELATIVE && o->tol_mode != L0_TOL_ABSOLUTE) return false;
     if (o->block_threads != 0 && o->block_threads != 256 && o->block_threads != 512) return false;
     return o->words_cap == 0 || (o->words_cap >= 64 && o->words_cap <= 32768);

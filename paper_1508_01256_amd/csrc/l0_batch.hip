@@ -282,9 +282,10 @@ __device__ void vote_pass(gptr<const int32_t> col_idx, int64_t n, const BlockSta
     if (!SPILL && lane == 0) L.wq[wid] = count;
 }
 
+// Exact score of column j (shifted rules: the candidate at position pos).
 template <int D>
 __device__ void score_column(gptr<const int32_t> col_idx, const BlockState& s, int rule, gptr<TeamCtl> ctl,
-                             gptr<IterCounters> ring, int64_t j, double tau, int a) {
+                             gptr<IterCounters> ring, int64_t j, double tau, int a, int pos) {
     int rows[D];
     double v[D];
 #pragma unroll
@@ -292,7 +293,9 @@ __device__ void score_column(gptr<const int32_t> col_idx, const BlockState& s, i
 #pragma unroll
     for (int t = 0; t < D; ++t) v[t] = s.r[rows[t]];
     double w;
-    if (exact_score<D>(v, tau, rule, a, w)) apply_update<D>(s, &ring->tcount, &ctl->support, &ring->affc, j, w, rows);
+    const bool sel = rule_is_shifted(rule) ? exact_score_shifted<D>(v, pos, tau, rule, a, w)
+                                           : exact_score<D>(v, tau, rule, a, w);
+    if (sel) apply_update<D>(s, &ring->tcount, &ctl->support, &ring->affc, j, w, rows);
 }
 
 // The vote of one iteration for this member, with the exact scoring of the
@@ -300,7 +303,7 @@ __device__ void score_column(gptr<const int32_t> col_idx, const BlockState& s, i
 // columns then went to the team's shared list, scored after a team barrier.
 template <int D, bool WL>
 __device__ bool vote_and_score(gptr<const int32_t> col_idx, int64_t n, const BlockState& s, const Lds& L, int a,
-                               int rule, const Team& tm, gptr<IterCounters> ring, double tau) {
+                               int rule, const Team& tm, gptr<IterCounters> ring, double tau, int pos) {
     const int nw = blockDim.x >> 6, qcap = kBatchQueue / nw;
     const int64_t first = static_cast<int64_t>(tm.rank) * nw, stride = static_cast<int64_t>(tm.size) * nw;
     vote_pass<D, WL, false>(col_idx, n, s, L, a, rule, first, stride, nullptr);
@@ -318,7 +321,7 @@ __device__ bool vote_and_score(gptr<const int32_t> col_idx, int64_t n, const Blo
     for (int q = threadIdx.x; q < total; q += blockDim.x) {
         int w = 0, k = q;
         while (k >= L.wq[w]) k -= L.wq[w++];
-        score_column<D>(col_idx, s, rule, tm.ctl, ring, L.queue[w * (qcap + 64) + k], tau, a);
+        score_column<D>(col_idx, s, rule, tm.ctl, ring, L.queue[w * (qcap + 64) + k], tau, a, pos);
     }
     return false;
 }
@@ -572,22 +575,27 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         tim[2] = t_last - tim[0];
     }
 
-    int l = 0, outcome = L0_DEV_ABORTED;
+    // Counters and touched-row lists go by vote pass, which differs from the
+    // iteration under a shifted rule: a pass selecting nothing is followed by
+    // another (the next position), and D such passes in a row stall the run.
+    int l = 0, pass = 0, empty = 0, outcome = L0_DEV_ABORTED;
+    const bool shifted = rule_is_shifted(bp.rule);
     long long updates = 0;
     while (alive) {
         if (nnz == 0) { outcome = L0_CONVERGED; break; }
         if (l == P.max_iter) { outcome = L0_MAX_ITER; break; }
-        const gptr<IterCounters> ring = &tm.ctl->ring[l % 3];
-        s.aff_list = s.aff_base + (l & 1) * m;
+        const gptr<IterCounters> ring = &tm.ctl->ring[pass % 3];
+        const int pos = pass % D;
+        s.aff_list = s.aff_base + (pass & 1) * m;
         if (tid == 0) L.ctr[0] = 0;
         __syncthreads();
 
         // vote and exact scoring of this member's columns (Jacobi updates)
-        const bool spilled = wl ? vote_and_score<D, true>(col_idx, n, s, L, a, bp.rule, tm, ring, tau)
-                                : vote_and_score<D, false>(col_idx, n, s, L, a, bp.rule, tm, ring, tau);
+        const bool spilled = wl ? vote_and_score<D, true>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos)
+                                : vote_and_score<D, false>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos);
         (void)spilled;
         if (lead && tid == 0) {
-            const gptr<IterCounters> next = &tm.ctl->ring[(l + 1) % 3];
+            const gptr<IterCounters> next = &tm.ctl->ring[(pass + 1) % 3];
             next->tcount = 0;
             next->affc = 0;
             next->spill = 0;
@@ -602,7 +610,8 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         // columns of overflowed queues, scored by the whole team
         const int nsp = load_agent(&ring->spill);
         if (nsp > 0) {
-            for (int64_t q = gt; q < nsp; q += gstep) score_column<D>(col_idx, s, bp.rule, tm.ctl, ring, s.overflow[q], tau, a);
+            for (int64_t q = gt; q < nsp; q += gstep)
+                score_column<D>(col_idx, s, bp.rule, tm.ctl, ring, s.overflow[q], tau, a, pos);
             if (!(alive = team_sync(tm, L))) break;
         }
         // support-list counts were raised by device-scope atomics: acquire
@@ -613,8 +622,14 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
             t_score += t - t_last;
             t_last = t;
         }
+        ++pass;
         const int tc = load_agent(&ring->tcount);
-        if (tc == 0) { outcome = L0_STALLED; break; }
+        if (tc == 0) {
+            if (shifted && ++empty < D) continue;
+            outcome = L0_STALLED;
+            break;
+        }
+        empty = 0;
 
         // residual update of the touched rows, split over the team; short
         // support lists one row per thread, long ones by this whole

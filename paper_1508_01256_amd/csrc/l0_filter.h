@@ -17,9 +17,17 @@
 
 namespace l0 {
 
-// Scoring rules (same values as l0_rule in l0decode.h).
+// Scoring rules (same values as l0_rule in l0decode.h).  The shifted rules
+// score one candidate per column per vote pass (Algorithm 3).
 constexpr int kRuleL0dec = 0;
 constexpr int kRuleMode = 1;
+constexpr int kRuleShiftedL0dec = 2;
+constexpr int kRuleShiftedMode = 3;
+
+L0_HD bool rule_is_shifted(int rule) { return rule >= kRuleShiftedL0dec; }
+
+// Rules whose score subtracts the zero entries (the l0-decrease c - z).
+L0_HD bool rule_counts_zeros(int rule) { return rule == kRuleL0dec || rule == kRuleShiftedL0dec; }
 
 // The score itself, by its definition, on the column's gathered residual
 // values v[0..D): for every nonzero candidate v[t], c counts the entries u with
@@ -48,6 +56,30 @@ L0_HD bool exact_score(const double (&v)[D], double tau, int rule, int a,
     }
     omega = w;
     return top != INT_MIN && top >= a;
+}
+
+// The shifted score (Algorithm 3): the only candidate is v[t], tried when
+// nonzero; c counts the entries within tau of it, the score is c - z (c for
+// the frequency rule) and the column is selected when it reaches a, with
+// omega = v[t].
+template <int D>
+L0_HD bool exact_score_shifted(const double (&v)[D], int t, double tau, int rule, int a, double& omega) {
+    omega = 0.0;
+    double cand = v[0];
+#pragma unroll
+    for (int u = 1; u < D; ++u)
+        if (u == t) cand = v[u];
+    if (!(std::fabs(cand) > tau)) return false;
+    int z = 0, c = 0;
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+        z += !(std::fabs(v[u]) > tau);
+        c += !(std::fabs(v[u] - cand) > tau);
+    }
+    const int score = rule_counts_zeros(rule) ? c - z : c;
+    if (score < a) return false;
+    omega = cand;
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -168,7 +200,7 @@ L0_HD bool bucket_filter(const uint32_t (&w)[D], int a, int rule) {
     int z = 0;
 #pragma unroll
     for (int k = 0; k < L; ++k) z |= static_cast<int>(c[k] >> 31) << k;
-    const int need = a + (rule == kRuleL0dec ? z : 0);
+    const int need = a + (rule_counts_zeros(rule) ? z : 0);
     // need > D can never be met; tested without a branch (the comparison
     // below only sees need's low L bits then, and its result is discarded)
     const bool reachable = need <= D;

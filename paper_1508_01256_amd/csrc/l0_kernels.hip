@@ -173,8 +173,9 @@ __device__ void write_result(const SolveParams& p, int iters, int outcome, int n
 
 // Exact scoring of one column that passed the bucket filter: its rows come
 // from the repacked index store, its values from the FP64 residual.
+// (Shifted rules: the one candidate of this pass, at position pos.)
 template <int D, bool COMPACT>
-__device__ void score_exact(const SolveParams& p, int l, int64_t j, double tau) {
+__device__ void score_exact(const SolveParams& p, int l, int64_t j, double tau, int pos) {
     int rows[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) rows[t] = soa_row<COMPACT>(p.soa, j, t, D);
@@ -182,8 +183,9 @@ __device__ void score_exact(const SolveParams& p, int l, int64_t j, double tau) 
 #pragma unroll
     for (int t = 0; t < D; ++t) v[t] = p.r[rows[t]];
     double w;
-    if (exact_score<D>(v, tau, p.rule, p.a, w))
-        apply_update<D>(p, &p.tcount[l], &p.ctrl->support, &p.affc[l], j, w, rows);
+    const bool sel = rule_is_shifted(p.rule) ? exact_score_shifted<D>(v, pos, tau, p.rule, p.a, w)
+                                             : exact_score<D>(v, tau, p.rule, p.a, w);
+    if (sel) apply_update<D>(p, &p.tcount[l], &p.ctrl->support, &p.affc[l], j, w, rows);
 }
 
 constexpr int kQueue = 2048;  // per-workgroup queue of columns passing the filter
@@ -210,7 +212,7 @@ __device__ __forceinline__ void load_chunk(const void* soa, uint32_t g, uint32_t
 // Filter the columns of one chunk; passing columns are compacted per wave into
 // the workgroup's LDS queue, or the global overflow queue once it is full.
 template <int D>
-__device__ __forceinline__ void filter_and_queue(const SolveParams& p, int l, const uint32_t (&w)[D],
+__device__ __forceinline__ void filter_and_queue(const SolveParams& p, int os, const uint32_t (&w)[D],
                                                  uint32_t j, uint32_t n, uint32_t lane, int* q_items,
                                                  int* q_count) {
     const bool pass = bucket_filter<D>(w, p.a, p.rule) && j < n;
@@ -224,7 +226,7 @@ __device__ __forceinline__ void filter_and_queue(const SolveParams& p, int l, co
             if (pos < kQueue) {
                 q_items[pos] = static_cast<int>(j);
             } else {
-                const int gp = atomicAdd(&p.ovc[l], 1);
+                const int gp = atomicAdd(&p.ovc[os], 1);
                 p.overflow[gp] = static_cast<int>(j);
             }
         }
@@ -235,9 +237,11 @@ __device__ __forceinline__ void filter_and_queue(const SolveParams& p, int l, co
 // indices while the current chunk gathers its rows' bucket words and runs the
 // bucket filter.  Columns passing it are scored exactly once the chunks are
 // done, on the same residual.
+// l: the iteration (update counters); os: the overflow-count slot of this
+// pass; pos: the position shifted rules try in this pass.
 template <int D, bool COMPACT>
 __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32_t* lds_w,
-                           int* q_items, int* q_count) {
+                           int* q_items, int* q_count, int os, int pos) {
     const uint32_t lane = threadIdx.x & 63;
     constexpr uint32_t kCols = Chunk<COMPACT>::kCols;
     const uint32_t nchunks = static_cast<uint32_t>(p.ntiles) * Chunk<COMPACT>::kPerTile;
@@ -260,13 +264,13 @@ __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32
                 uint32_t w[D];
 #pragma unroll
                 for (int t = 0; t < D; ++t) w[t] = words[h ? (cur[t] >> 16) : (cur[t] & 0xFFFFu)];
-                filter_and_queue<D>(p, l, w, g * kCols + 2 * lane + h, n, lane, q_items, q_count);
+                filter_and_queue<D>(p, os, w, g * kCols + 2 * lane + h, n, lane, q_items, q_count);
             }
         } else {
             uint32_t w[D];
 #pragma unroll
             for (int t = 0; t < D; ++t) w[t] = words[cur[t]];
-            filter_and_queue<D>(p, l, w, g * kCols + lane, n, lane, q_items, q_count);
+            filter_and_queue<D>(p, os, w, g * kCols + lane, n, lane, q_items, q_count);
         }
 #pragma unroll
         for (int t = 0; t < D; ++t) cur[t] = nxt[t];
@@ -275,7 +279,7 @@ __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32
     if (p.timeline && blockIdx.x == 0 && threadIdx.x == 0)
         p.timeline[3 * p.max_iter + 9 + 3 * l] = static_cast<int64_t>(wall_clock64());
     const int cnt = min(*q_count, kQueue);
-    for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D, COMPACT>(p, l, q_items[q], tau);
+    for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D, COMPACT>(p, l, q_items[q], tau, pos);
     __syncthreads();
     if (threadIdx.x == 0) {
         *q_count = 0;
@@ -386,12 +390,20 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     int nnz = ld_relaxed(&c->nnz);
     if (gtid == 0 && p.trace) p.trace[0] = nnz;
 
-    int l = 0;
+    // Vote passes are counted apart from iterations: a shifted rule's pass
+    // that selects nothing is followed by another (the next position) and
+    // the run stalls after D such passes in a row.  Overflow counts use a
+    // ring of three slots by pass: slot pass+1 was last read before the
+    // barrier that ended pass - 1, so thread 0 clears it during this pass.
+    int l = 0, pass = 0, empty = 0;
+    const bool shifted = rule_is_shifted(p.rule);
     int outcome;
     long long updates = 0;
     for (;;) {
         if (nnz == 0) { outcome = L0_CONVERGED; break; }
         if (l == p.max_iter) { outcome = L0_MAX_ITER; break; }
+        const int os = pass % 3, pos = pass % D;
+        if (gtid == 0) p.ovc[(pass + 1) % 3] = 0;
 
         // vote on the same residual for every column
         if (COMPACT) {
@@ -410,23 +422,29 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             if (p.timeline && blockIdx.x == 0 && tid == 0)
                 p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
         }
-        vote_phase<D, COMPACT>(p, l, tau, lds_w, q_items, &q_count);
+        vote_phase<D, COMPACT>(p, l, tau, lds_w, q_items, &q_count, os, pos);
         if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
             return;
         }
         // columns that overflowed the workgroup queues are scored now, still
         // on the residual every other column saw
-        const int novf = ld_relaxed(&p.ovc[l]);
+        const int novf = ld_relaxed(&p.ovc[os]);
         if (novf > 0) {
-            for (int64_t q = gtid; q < novf; q += gsize) score_exact<D, COMPACT>(p, l, p.overflow[q], tau);
+            for (int64_t q = gtid; q < novf; q += gsize) score_exact<D, COMPACT>(p, l, p.overflow[q], tau, pos);
             if (!grid_sync(c, site, limit, p.timeline)) {
                 if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
                 return;
             }
         }
+        ++pass;
         const int tc = ld_relaxed(&p.tcount[l]);
-        if (tc == 0) { outcome = L0_STALLED; break; }
+        if (tc == 0) {
+            if (shifted && ++empty < D) continue;
+            outcome = L0_STALLED;
+            break;
+        }
+        empty = 0;
 
         // residual update of the touched rows, ||r||_0 by its change
         {

@@ -81,7 +81,7 @@ bool server_opts_ok(const l0_server_opts* o) {
     if (o->max_batch < 0 || o->max_inflight < 0 || o->max_inflight > kMaxSlots) return false;
     const l0_batch_opts& b = o->batch;
     if (b.timing) return false;
-    if (b.rule != L0_RULE_L0DEC && b.rule != L0_RULE_MODE) return false;
+    if ((b.rule < L0_RULE_L0DEC || b.rule > L0_RULE_SHIFTED_MODE)) return false;
     if (b.tol_mode != L0_TOL_RELATIVE && b.tol_mode != L0_TOL_ABSOLUTE) return false;
     if (b.block_threads != 0 && b.block_threads != 256 && b.block_threads != 512) return false;
     return b.words_cap == 0 || (b.words_cap >= 64 && b.words_cap <= 32768);

@@ -95,6 +95,7 @@ static int check_exactness(int trials) {
             for (int rule = 0; rule < 2; ++rule)
                 for (int a = 2; a <= D; ++a) {
                     // definition: decrease of ||r||_0 over the column's rows
+                    // (rules 0, 1; their shifted forms 2, 3 below)
                     int best = INT_MIN;
                     double wbest = 0.0;
                     for (int t = 0; t < D; ++t) {
@@ -123,6 +124,34 @@ static int check_exactness(int trials) {
                         std::printf("FILTER REJECTED A SELECTED COLUMN D=%d tau=%g a=%d rule=%d\n", D, tau, a, rule);
                         for (int t = 0; t < D; ++t) std::printf("  v=%.17g w=%08x\n", v[t], w[t]);
                         return 1;
+                    }
+                    // shifted rule (Algorithm 3): candidate v[t] only, by its
+                    // definition; the filter (with the shifted rule's zero
+                    // term) must pass every column it selects
+                    const int srule = rule + 2;
+                    for (int t = 0; t < D; ++t) {
+                        bool sdef = false;
+                        if (std::fabs(v[t]) > tau) {
+                            int before = 0, after = 0, freq = 0;
+                            for (int u = 0; u < D; ++u) {
+                                before += std::fabs(v[u]) > tau;
+                                const double dlt = v[u] - v[t];
+                                after += std::fabs(dlt) > tau;
+                                freq += !(std::fabs(dlt) > tau);
+                            }
+                            sdef = (rule == kRuleMode ? freq : before - after) >= a;
+                        }
+                        double som = 0.0;
+                        const bool ssel = exact_score_shifted<D>(v, t, tau, srule, a, som);
+                        if (ssel != sdef || (ssel && som != v[t])) {
+                            std::printf("exact_score_shifted D=%d t=%d mismatch\n", D, t);
+                            return 1;
+                        }
+                        if (ssel && !bucket_filter<D>(w, a, srule)) {
+                            std::printf("FILTER REJECTED A SHIFTED SELECTION D=%d tau=%g a=%d rule=%d\n", D, tau, a,
+                                        srule);
+                            return 1;
+                        }
                     }
                 }
         }

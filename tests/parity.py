@@ -8,7 +8,8 @@ import torch
 import oracle
 import paper_1508_01256_amd as l0
 
-RULE_MAP = {l0.L0_RULE_L0DEC: oracle.RULE_L0DEC, l0.L0_RULE_MODE: oracle.RULE_MODE}
+RULE_MAP = {l0.L0_RULE_L0DEC: oracle.RULE_L0DEC, l0.L0_RULE_MODE: oracle.RULE_MODE,
+            l0.L0_RULE_SHIFTED_L0DEC: oracle.RULE_SHIFTED_L0DEC, l0.L0_RULE_SHIFTED_MODE: oracle.RULE_SHIFTED_MODE}
 
 
 def say(*a):

@@ -120,7 +120,7 @@ def test_batched_bad_options_and_counts():
     assert L.l0_decode_batched(None, 2, None, None, None, 0, None) == l0.L0_ERR_ARG
     assert L.l0_decode_batched(t, 0, None, None, None, 0, None) == l0.L0_ERR_ARG
     assert L.l0_batch_workspace_bytes(t, 0, None) == 0
-    for o in [l0.l0_batch_opts(rule=2), l0.l0_batch_opts(tol_mode=2),
+    for o in [l0.l0_batch_opts(rule=4), l0.l0_batch_opts(tol_mode=2),
               l0.l0_batch_opts(block_threads=128), l0.l0_batch_opts(block_threads=1024),
               l0.l0_batch_opts(words_cap=-1), l0.l0_batch_opts(words_cap=63),
               l0.l0_batch_opts(words_cap=40000)]:
@@ -187,7 +187,7 @@ def test_server_argument_errors():
     for o in [l0.l0_server_opts(0, 0, 0, l0.l0_batch_opts()),
               l0.l0_server_opts(1 << 20, -1, 0, l0.l0_batch_opts()),
               l0.l0_server_opts(1 << 20, 0, 5, l0.l0_batch_opts()),
-              l0.l0_server_opts(1 << 20, 0, 0, l0.l0_batch_opts(rule=3)),
+              l0.l0_server_opts(1 << 20, 0, 0, l0.l0_batch_opts(rule=4)),
               l0.l0_server_opts(1 << 20, 0, 0, l0.l0_batch_opts(block_threads=1024)),
               l0.l0_server_opts(1 << 20, 0, 0, l0.l0_batch_opts(timing=1))]:
         assert L.l0_server_create(ctypes.byref(o), ctypes.byref(h)) == l0.L0_ERR_ARG

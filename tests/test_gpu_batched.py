@@ -205,3 +205,13 @@ def test_teams_with_small_grid_schedule():
     insts = [gen.make_instance(45, 1 << 20, 10486, 9, 1000), gen.make_instance(46, 300000, 30000, 5, 2500)]
     res = batched_run(insts, block_threads=256, words_cap=8192)
     check_all(insts, res, "teams-256")
+
+
+@pytest.mark.parametrize("rule", [l0.L0_RULE_SHIFTED_L0DEC, l0.L0_RULE_SHIFTED_MODE])
+def test_shifted_rules_in_a_batch(rule):
+    """Shifted Parallel-l0 on a mixed batch, including a team-decoded
+    instance; each against the oracle's shifted run."""
+    insts = sweep_like(60, 31, n_max_log2=13) + [gen.make_instance(47, 1 << 20, 10486, 7, 900)]
+    alphas = [2.0 if q % 2 else float(i.alpha) for q, i in enumerate(insts)]
+    res = batched_run(insts, alphas=alphas, rule=rule)
+    check_all(insts, res, f"shifted{rule}", alphas=alphas, rule=rule)

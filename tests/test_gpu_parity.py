@@ -12,7 +12,8 @@ from parity import assert_parity, gpu_run, oracle_run, run_both, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
-RULES = {"L0DEC": l0.L0_RULE_L0DEC, "MODE": l0.L0_RULE_MODE}
+RULES = {"L0DEC": l0.L0_RULE_L0DEC, "MODE": l0.L0_RULE_MODE, "SHIFTED_L0DEC": l0.L0_RULE_SHIFTED_L0DEC,
+         "SHIFTED_MODE": l0.L0_RULE_SHIFTED_MODE}
 OUT = {"CONVERGED": l0.L0_CONVERGED, "STALLED": l0.L0_STALLED, "MAX_ITER": l0.L0_MAX_ITER}
 
 
@@ -50,6 +51,29 @@ def test_small_workload_mode_rule(seed):
     inst = gen.single_workload("small", seed)
     g, o = run_both(inst, rule=l0.L0_RULE_MODE)
     assert_parity(g, o, label=f"small-mode/{seed}")
+
+
+@pytest.mark.parametrize("rule", [l0.L0_RULE_SHIFTED_L0DEC, l0.L0_RULE_SHIFTED_MODE])
+@pytest.mark.parametrize("seed", range(4))
+def test_small_workload_shifted_rules(seed, rule):
+    """Shifted Parallel-l0 (Algorithm 3): one candidate per column per pass."""
+    inst = gen.make_instance(700 + seed, 4096, 512, 7, 20 + 10 * seed)
+    for alpha in (2.0, 4.0):
+        g, o = run_both(inst, alpha=alpha, rule=rule)
+        assert_parity(g, o, label=f"shifted-{rule}-{seed}-{alpha}")
+
+
+@pytest.mark.parametrize("n,m,d,k", [
+    (400000, 40000, 7, 3000),   # 32-bit rows, words from L2
+    (262144, 26215, 7, 2621),   # 16-bit rows
+    (50000, 5000, 9, 300),
+    (3000, 60, 3, 8),           # tiny m: many overflowing passes
+])
+def test_shapes_shifted(n, m, d, k):
+    inst = gen.make_instance(5151 + n + d, n, m, d, k)
+    say("shifted shape", n, m, d, k)
+    g, o = run_both(inst, rule=l0.L0_RULE_SHIFTED_L0DEC)
+    assert_parity(g, o, label=f"shifted {n}/{m}/{d}/{k}")
 
 
 @pytest.mark.parametrize("n,m,d,k", [
