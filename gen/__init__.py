@@ -57,8 +57,11 @@ def _load():
         lib.l0gen_support.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, P]
         lib.l0gen_values.argtypes = [ctypes.c_uint64, ctypes.c_int64, P, ctypes.c_int32, P]
         lib.l0gen_measure.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
-                                      ctypes.c_int64, P, P, P]
-        for f in (lib.l0gen_columns, lib.l0gen_support, lib.l0gen_values, lib.l0gen_measure):
+                                      ctypes.c_int64, P, P, P, P]
+        lib.l0gen_weights.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_double,
+                                      ctypes.c_double, P]
+        for f in (lib.l0gen_columns, lib.l0gen_support, lib.l0gen_values, lib.l0gen_measure,
+                  lib.l0gen_weights):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -93,14 +96,30 @@ def values(seed: int, supp: np.ndarray, kind: int = VALUES_NORMAL) -> np.ndarray
     return out
 
 
+def weights(seed: int, n: int, lo: float = 0.5, hi: float = 1.5) -> np.ndarray:
+    """float64[n]: per-column weights of a column-scaled A, uniform on [lo, hi]."""
+    out = np.empty(n, dtype=np.float64)
+    if _load().l0gen_weights(seed, n, lo, hi, _ptr(out)) != 0:
+        raise ValueError(f"bad weight arguments n={n} lo={lo} hi={hi}")
+    return out
+
+
 def measure(n: int, m: int, d: int, col_idx: np.ndarray, supp: np.ndarray,
-            vals: np.ndarray) -> np.ndarray:
-    """float64[m]: y = A x, each y_i summed from +0.0 over ascending columns."""
+            vals: np.ndarray, w: np.ndarray | None = None) -> np.ndarray:
+    """float64[m]: y = A x, each y_i summed from +0.0 over ascending columns;
+    with weights w, column j of A holds w[j] and each term is fl(w[j] x_j)."""
     col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
     supp = np.ascontiguousarray(supp, dtype=np.int64)
     vals = np.ascontiguousarray(vals, dtype=np.float64)
+    wp = None
+    if w is not None:
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        if w.shape != (n,):
+            raise ValueError("weights must have n entries")
+        wp = _ptr(w)
     y = np.empty(m, dtype=np.float64)
-    if _load().l0gen_measure(n, m, d, _ptr(col_idx), supp.size, _ptr(supp), _ptr(vals), _ptr(y)) != 0:
+    if _load().l0gen_measure(n, m, d, _ptr(col_idx), supp.size, _ptr(supp), _ptr(vals), wp,
+                             _ptr(y)) != 0:
         raise ValueError("bad measurement arguments")
     return y
 
@@ -119,6 +138,7 @@ class Instance:
     y: np.ndarray         # float64[m]
     alpha: float
     kind: int = VALUES_NORMAL
+    w: np.ndarray | None = None  # float64[n] column weights (column-scaled A), or None
 
     @property
     def x(self) -> np.ndarray:
@@ -133,14 +153,16 @@ def default_alpha(d: int) -> float:
 
 
 def make_instance(seed: int, n: int, m: int, d: int, k: int, *, alpha: float | None = None,
-                  kind: int = VALUES_NORMAL) -> Instance:
-    """Draw A, a k-sparse x and y = A x; alpha defaults to default_alpha(d)."""
+                  kind: int = VALUES_NORMAL, scaled: bool = False) -> Instance:
+    """Draw A, a k-sparse x and y = A x; alpha defaults to default_alpha(d).
+    With scaled=True, A's columns carry weights uniform on [1/2, 3/2]."""
     col = columns(seed, n, m, d)
     supp = support(seed, n, k)
     vals = values(seed, supp, kind)
-    y = measure(n, m, d, col, supp, vals)
+    w = weights(seed, n) if scaled else None
+    y = measure(n, m, d, col, supp, vals, w)
     a = default_alpha(d) if alpha is None else float(alpha)
-    return Instance(n, m, d, k, seed, col, supp, vals, y, a, kind)
+    return Instance(n, m, d, k, seed, col, supp, vals, y, a, kind, w)
 
 
 # ---------------------------------------------------------------------------

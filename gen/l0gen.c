@@ -25,7 +25,7 @@
 
 #define GAMMA 0x9E3779B97F4A7C15ULL
 
-enum { TAG_COLUMNS = 1, TAG_SUPPORT = 2, TAG_VALUES = 3 };
+enum { TAG_COLUMNS = 1, TAG_SUPPORT = 2, TAG_VALUES = 3, TAG_WEIGHTS = 4 };
 
 static inline uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -126,22 +126,40 @@ int l0gen_values(uint64_t seed, int64_t k, const int64_t* supp, int32_t kind, do
 }
 
 /*
+ * Column weights for a column-scaled matrix (Section 4.3.3: every column of A
+ * multiplied by an i.i.d. draw from a continuous distribution): w_j uniform
+ * on [lo, hi] (a 53-bit draw scaled to the interval), from column j's own
+ * stream.  Returns 0 or -1.
+ */
+int l0gen_weights(uint64_t seed, int64_t n, double lo, double hi, double* w) {
+    if (n < 0 || (n > 0 && !w) || !(lo < hi) || !isfinite(lo) || !isfinite(hi)) return -1;
+    for (int64_t j = 0; j < n; ++j) {
+        uint64_t key = stream_key(seed, TAG_WEIGHTS, (uint64_t)j);
+        uint64_t ctr = 0;
+        w[j] = lo + (hi - lo) * unit53(key, &ctr);
+    }
+    return 0;
+}
+
+/*
  * Measurement y = A x for x given by (supp, vals), supp ascending:
  * y_i is the sum, starting from +0.0 and taken over ascending column index,
- * of x_j over the support columns j whose neighbourhood contains row i.
- * Returns 0 or -1.
+ * of the entries A_ij x_j over the support columns j whose neighbourhood
+ * contains row i.  A_ij is 1, or w[j] when w is given (each product rounded
+ * once before it is added).  Returns 0 or -1.
  */
 int l0gen_measure(int64_t n, int32_t m, int32_t d, const int32_t* col_idx,
-                  int64_t k, const int64_t* supp, const double* vals, double* y) {
+                  int64_t k, const int64_t* supp, const double* vals, const double* w, double* y) {
     if (n < 0 || m < 1 || d < 1 || !y || (k > 0 && (!col_idx || !supp || !vals))) return -1;
     for (int32_t i = 0; i < m; ++i) y[i] = 0.0;
     for (int64_t s = 0; s < k; ++s) {
         int64_t j = supp[s];
         if (j < 0 || j >= n || (s > 0 && supp[s - 1] >= j)) return -1;
+        const double term = w ? w[j] * vals[s] : vals[s];
         for (int32_t t = 0; t < d; ++t) {
             int32_t i = col_idx[j * (int64_t)d + t];
             if (i < 0 || i >= m) return -1;
-            y[i] += vals[s];
+            y[i] += term;
         }
     }
     return 0;

@@ -47,11 +47,11 @@ def _load():
             build(force=False)
         lib = ctypes.CDLL(_LIB)
         P, I32, I64, F64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-        lib.orc_parallel_l0.argtypes = [I64, I32, I32, P, P, F64, I32, I32, F64, P, P, P, P, P, P, P]
+        lib.orc_parallel_l0.argtypes = [I64, I32, I32, P, P, F64, I32, I32, F64, P, P, P, P, P, P, P, P]
         lib.orc_parallel_l0.restype = ctypes.c_int
         lib.orc_serial_l0.argtypes = [I64, I32, I32, P, P, F64, I32, I32, F64, P, P, P, P, P]
         lib.orc_serial_l0.restype = ctypes.c_int
-        lib.orc_residual.argtypes = [I64, I32, I32, P, P, P, P]
+        lib.orc_residual.argtypes = [I64, I32, I32, P, P, P, P, P]
         lib.orc_residual.restype = None
         lib.orc_score_columns.argtypes = [I64, I32, P, P, F64, I32, I32, P, P, P]
         lib.orc_score_columns.restype = None
@@ -72,18 +72,22 @@ def _c(a, dt):
 
 
 def parallel_l0(n, m, d, col_idx, y, alpha, *, max_iter=100, tol=1e-10, rule=RULE_L0DEC,
-                x_init=None):
+                x_init=None, w=None):
     """Run Parallel-l0 (rules L0DEC, MODE) or its shifted form (Algorithm 3;
-    rules SHIFTED_L0DEC, SHIFTED_MODE); returns dict(x, iters, outcome, trace,
-    tsize, passes) where passes counts vote passes."""
+    rules SHIFTED_L0DEC, SHIFTED_MODE), on a column-scaled A when column
+    weights w are given (Section 4.3.3); returns dict(x, iters, outcome,
+    trace, tsize, passes) where passes counts vote passes."""
     col_idx, y = _c(col_idx, np.int32), _c(y, np.float64)
     xi = None if x_init is None else _c(x_init, np.float64)
+    wv = None if w is None else _c(w, np.float64)
+    if wv is not None and wv.shape != (n,):
+        raise ValueError("weights must have n entries")
     x = np.empty(n, dtype=np.float64)
     trace = np.zeros(max_iter + 1, dtype=np.int32)
     tsize = np.zeros(max(max_iter, 1), dtype=np.int64)
     iters, outcome, passes = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     rc = _load().orc_parallel_l0(n, m, d, _p(col_idx), _p(y), float(alpha), rule, max_iter,
-                                 float(tol), _p(xi), _p(x), _p(trace), _p(tsize),
+                                 float(tol), _p(xi), _p(wv), _p(x), _p(trace), _p(tsize),
                                  ctypes.byref(iters), ctypes.byref(outcome), ctypes.byref(passes))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
@@ -105,11 +109,13 @@ def serial_l0(n, m, d, col_idx, y, alpha, *, max_sweeps=100, tol=1e-10, rule=RUL
     return dict(x=x, updates=upd.value, sweeps=sw.value, outcome=oc.value, final_nnz=nnz.value)
 
 
-def residual(n, m, d, col_idx, y, x):
-    """r = y - A x with ascending-column sums from +0.0."""
+def residual(n, m, d, col_idx, y, x, w=None):
+    """r = y - A x with ascending-column sums from +0.0 (column weights w, if
+    given, multiply each term once before it is added)."""
     col_idx, y, x = _c(col_idx, np.int32), _c(y, np.float64), _c(x, np.float64)
+    wv = None if w is None else _c(w, np.float64)
     r = np.empty(m, dtype=np.float64)
-    _load().orc_residual(n, m, d, _p(col_idx), _p(y), _p(x), _p(r))
+    _load().orc_residual(n, m, d, _p(col_idx), _p(y), _p(x), _p(wv), _p(r))
     return r
 
 

@@ -38,6 +38,19 @@
  * tries other positions, so the run stalls only after d consecutive empty
  * passes.  Readings: p counts vote passes, not residual updates; "the
  * (p mod d)-th element of r_N(j)" is taken in col_idx order.
+ *
+ * Column-scaled A (Section 4.3.3): optional weights w[n], w_j > 0 and finite,
+ * make column j of A hold w_j on its d rows, so y_i sums w_j x_j.  Readings:
+ *  - the update that zeroes entry t of r_N(j) is omega = r_t / w_j; entry u
+ *    of r - omega a_j is then r_u - r_t in exact arithmetic, and it is
+ *    evaluated as such, so a column's scores and its chosen entry t are those
+ *    of the unscaled rule on the same r (every rule above), and only the
+ *    update becomes fl(r_t / w_j);
+ *  - w_j > 0 keeps the order of the candidates (the smallest r_t gives the
+ *    smallest omega), so the tie-break is unchanged;
+ *  - the residual sums the rounded products fl(w_j x_hat_j), from +0.0 over
+ *    ascending columns.
+ * Without weights every formula reduces to the unit-weight one bit for bit.
  */
 #include <limits.h>
 #include <math.h>
@@ -104,6 +117,13 @@ static int score_column_shifted(int32_t d, const double* v, int32_t t, double ta
     return 1;
 }
 
+static int weights_ok(int64_t n, const double* w) {
+    if (!w) return 1;
+    for (int64_t j = 0; j < n; ++j)
+        if (!(w[j] > 0.0) || !isfinite(w[j])) return 0;
+    return 1;
+}
+
 static int args_ok(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const double* y,
                    double alpha, int32_t rule, int32_t max_iter, double tol) {
     if (n < 1 || m < 1 || d < 2 || d > m || !col_idx || !y) return 0;
@@ -124,12 +144,15 @@ static double zero_threshold(int32_t m, const double* y, double tol) {
     return tol * s;
 }
 
-/* r = y - A x, each (A x)_i summed from +0.0 over ascending columns. */
+/* r = y - A x, each (A x)_i summed from +0.0 over ascending columns; with
+ * weights w (or NULL for unit columns) each term is the rounded w_j x_j. */
 void orc_residual(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const double* y,
-                  const double* x, double* r) {
+                  const double* x, const double* w, double* r) {
     double* s = (double*)calloc((size_t)m, sizeof(double));
-    for (int64_t j = 0; j < n; ++j)
-        for (int32_t t = 0; t < d; ++t) s[col_idx[j * d + t]] += x[j];
+    for (int64_t j = 0; j < n; ++j) {
+        const double term = w ? w[j] * x[j] : x[j];
+        for (int32_t t = 0; t < d; ++t) s[col_idx[j * d + t]] += term;
+    }
     for (int32_t i = 0; i < m; ++i) r[i] = y[i] - s[i];
     free(s);
 }
@@ -183,17 +206,18 @@ int32_t orc_literal_decrease(int32_t m, int32_t d, const int32_t* rows, const do
 
 /*
  * Parallel-l0 (Algorithm 2).  x_init (optional) resumes from a previous
- * estimate; x_out[n] receives x_hat.  trace[0..iters] receives ||r||_0 after
+ * estimate; w (optional) gives the column weights of a column-scaled A;
+ * x_out[n] receives x_hat.  trace[0..iters] receives ||r||_0 after
  * each residual update (trace[0] for the start), tsize[0..iters) the number
  * of columns updated in each iteration; both need max_iter+1 / max_iter
  * slots.  Returns 0, or -1 on invalid arguments.
  */
 int orc_parallel_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const double* y,
                     double alpha, int32_t rule, int32_t max_iter, double tol, const double* x_init,
-                    double* x_out, int32_t* trace, int64_t* tsize, int32_t* iters,
+                    const double* w, double* x_out, int32_t* trace, int64_t* tsize, int32_t* iters,
                     int32_t* outcome, int32_t* passes) {
-    if (!args_ok(n, m, d, col_idx, y, alpha, rule, max_iter, tol) || !x_out || !trace || !iters ||
-        !outcome)
+    if (!args_ok(n, m, d, col_idx, y, alpha, rule, max_iter, tol) || !weights_ok(n, w) || !x_out ||
+        !trace || !iters || !outcome)
         return -1;
     const int32_t a = (int32_t)ceil(alpha);
     const double tau = zero_threshold(m, y, tol);
@@ -203,7 +227,7 @@ int orc_parallel_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, con
     uint8_t* sel = (uint8_t*)malloc((size_t)n);
 
     for (int64_t j = 0; j < n; ++j) x_out[j] = x_init ? x_init[j] : 0.0;
-    orc_residual(n, m, d, col_idx, y, x_out, r);
+    orc_residual(n, m, d, col_idx, y, x_out, w, r);
     const int shifted = rule == ORC_RULE_SHIFTED_L0DEC || rule == ORC_RULE_SHIFTED_MODE;
     int32_t l = 0, p = 0, empty = 0;
     trace[0] = count_nonzero(m, r, tau);
@@ -229,9 +253,11 @@ int orc_parallel_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, con
             break;
         }
         empty = 0;
+        /* omega[j] is the residual value the update cancels; on a scaled
+           column the update itself is that value over w_j */
         for (int64_t j = 0; j < n; ++j)
-            if (sel[j]) x_out[j] = x_out[j] + omega[j];
-        orc_residual(n, m, d, col_idx, y, x_out, r);
+            if (sel[j]) x_out[j] = x_out[j] + (w ? omega[j] / w[j] : omega[j]);
+        orc_residual(n, m, d, col_idx, y, x_out, w, r);
         if (tsize) tsize[l] = chosen;
         ++l;
         trace[l] = count_nonzero(m, r, tau);

@@ -38,11 +38,16 @@ def test_scorer_cases():
 def test_worked_decodes(case):
     name, g, y, x, c = case
     n, m, d, col = graph_arrays(g)
-    # the fixture's y is the measurement of its x
-    assert np.array_equal(brute.dense_matrix(n, m, d, col) @ x, y)
+    w = np.array(g["w"], float) if "w" in g else None
+    # the fixture's y is the measurement of its x (column-scaled when w is given)
+    dense = brute.dense_matrix(n, m, d, col)
+    if w is not None:
+        dense = dense * w[None, :]
+    assert np.array_equal(dense @ x, y)
+    assert c.get("weights", False) == (w is not None)
     if c["algo"] == "parallel":
         res = oracle.parallel_l0(n, m, d, col, y, c["alpha"], max_iter=c["max_iter"], tol=c["tol"],
-                                 rule=RULES[c["rule"]])
+                                 rule=RULES[c["rule"]], w=w)
         assert res["trace"].tolist() == c["trace"]
         assert res["tsize"].tolist() == c["tsize"]
         assert res["iters"] == c["iters"]

@@ -11,12 +11,17 @@ import pytest
 
 import oracle
 import test_oracle as pins
+import test_oracle_scaled as cpins
 import test_oracle_shifted as spins
 from golden_io import decode_cases
 
 MUTANTS = {
     "residual_sign": ("r[i] = y[i] - s[i];", "r[i] = y[i] + s[i];"),
-    "update_sign": ("x_out[j] = x_out[j] + omega[j];", "x_out[j] = x_out[j] - omega[j];"),
+    "update_sign": ("x_out[j] = x_out[j] + (w ?", "x_out[j] = x_out[j] - (w ?"),
+    "scaled_update_multiplies": ("(w ? omega[j] / w[j] : omega[j])", "(w ? omega[j] * w[j] : omega[j])"),
+    "scaled_residual_unweighted": ("const double term = w ? w[j] * x[j] : x[j];", "const double term = x[j];"),
+    "scaled_residual_weight_index": ("const double term = w ? w[j] * x[j] : x[j];",
+                                     "const double term = w ? w[(j + 1) % n] * x[j] : x[j];"),
     "tie_break_largest": ("(score == top && v[t] < w)", "(score == top && v[t] > w)"),
     "drop_zero_count": ("(rule == ORC_RULE_MODE) ? freq : before - after;", "(rule == ORC_RULE_MODE) ? freq : d - after;"),
     "shift_drop_zero_count": ("(shifted_rule == ORC_RULE_SHIFTED_MODE) ? freq : before - after;",
@@ -58,6 +63,11 @@ def _run_pins():
         ("shift_subset", spins.test_shifted_selects_a_subset_of_the_full_vote),
         ("shift_closed", spins.test_shifted_k0_and_disjoint_columns),
         ("shift_theorem", lambda: spins.test_theorem_4_8_on_dissociated_signals(0)),
+        ("scaled_unit", lambda: cpins.test_unit_weights_are_the_unscaled_decoder(oracle.RULE_L0DEC)),
+        ("scaled_pow2", lambda: cpins.test_power_of_two_weights_decode_the_weighted_signal(oracle.RULE_L0DEC)),
+        ("scaled_literal", lambda: cpins.test_scaled_selection_is_the_literal_decrease(oracle.RULE_L0DEC)),
+        ("scaled_residual", cpins.test_scaled_residual_against_a_dense_product),
+        ("scaled_pm1", lambda: cpins.test_pm1_signals_recovered_only_with_scaled_columns(0)),
     ]
     for name, fn in checks:
         try:
