@@ -185,11 +185,12 @@ SINGLE = {
 }
 
 
-def single_workload(name: str, i: int = 0, kind: int = VALUES_NORMAL) -> Instance:
-    """Instance i of a single-instance workload ('small', 'n2^20', 'n2^24')."""
+def single_workload(name: str, i: int = 0, kind: int = VALUES_NORMAL, scaled: bool = False) -> Instance:
+    """Instance i of a single-instance workload ('small', 'n2^20', 'n2^24'),
+    on a column-scaled A when scaled is set."""
     c = {"small": 0, "n2^20": 1, "n2^24": 2}[name]
     n, m, d, k = SINGLE[name]
-    return make_instance(SEED + 1000 * c + i, n, m, d, k, kind=kind)
+    return make_instance(SEED + 1000 * c + i, n, m, d, k, kind=kind, scaled=scaled)
 
 
 def sweep_params(count: int = 4096, seed: int = SEED + 3000):

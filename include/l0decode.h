@@ -31,6 +31,16 @@
  *    ||r||_0 = 0 (L0_CONVERGED), when no column qualifies (L0_STALLED; r would
  *    never change again) or after max_iter iterations (L0_MAX_ITER).
  *    Non-convergence is an outcome, not an error.
+ *  - Column-scaled A (Section 4.3.3: columns multiplied by i.i.d. draws from
+ *    a continuous distribution, so that non-dissociated signals such as +-1
+ *    values become identifiable): optional weights w, device double[n] with
+ *    every w_j > 0 and finite, make column j hold w_j on its d rows.  A
+ *    column's scores and chosen residual value r_t are those above (entry u
+ *    of r - omega a_j is r_u - r_t once omega = r_t / w_j); the update is
+ *    x_hat_j += r_t / w_j, and the residual sums the rounded products
+ *    w_j * x_hat_j in ascending j.  Unit weights give bitwise the unweighted
+ *    result.  A weight that is not positive and finite ends the solve with
+ *    L0_DEV_BAD_WEIGHT before any update.
  *  - All pointers documented as "device" are device memory (hipMalloc or
  *    torch CUDA tensors) owned by the caller unless stated otherwise.  Every
  *    call is asynchronous and ordered on `stream`; outputs are valid after the
@@ -65,7 +75,8 @@ typedef enum {
     L0_MAX_ITER = 2,
     L0_DEV_BAD_INDEX = 16,   /* a row index outside [0, m) (when checked) */
     L0_DEV_NONFINITE_Y = 17, /* y holds NaN or Inf */
-    L0_DEV_ABORTED = 19      /* the device loop timed out waiting for itself */
+    L0_DEV_ABORTED = 19,     /* the device loop timed out waiting for itself */
+    L0_DEV_BAD_WEIGHT = 20   /* a column weight is zero, negative or not finite */
 } l0_outcome;
 
 typedef enum {
@@ -112,6 +123,8 @@ typedef struct {
                               entries 3*max_iter+8+3*l+{0,1,2} when the vote of iteration l
                               has staged the residual, streamed all columns, and scored the
                               columns that passed the filter */
+    const double* weights; /* device double[n] column weights of a column-scaled A
+                              (Section 4.3.3), or NULL for unit columns */
 } l0_opts;
 
 /* Library version string. */
@@ -213,6 +226,7 @@ typedef struct {
     int32_t reserved;       /* must be 0 */
     double tol;             /* >= 0, finite */
     double* x_out;          /* device double[n], receives x_hat */
+    const double* weights;  /* device double[n] column weights (Section 4.3.3), or NULL */
 } l0_problem;
 
 /* Launch schedule of l0_decode_batched; zero fields mean "default". */

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(HERE, "libl0decode.so")
 L0_OK, L0_ERR_ARG, L0_ERR_OOM, L0_ERR_HIP, L0_ERR_WORKSPACE = 0, 1, 2, 3, 4
 # outcomes (written on the device)
 L0_CONVERGED, L0_STALLED, L0_MAX_ITER = 0, 1, 2
-L0_DEV_BAD_INDEX, L0_DEV_NONFINITE_Y, L0_DEV_ABORTED = 16, 17, 19
+L0_DEV_BAD_INDEX, L0_DEV_NONFINITE_Y, L0_DEV_ABORTED, L0_DEV_BAD_WEIGHT = 16, 17, 19, 20
 OUTCOME_NAMES = {0: "CONVERGED", 1: "STALLED", 2: "MAX_ITER", 16: "DEV_BAD_INDEX",
                  17: "DEV_NONFINITE_Y", 19: "DEV_ABORTED"}
 # rules and tolerance modes
@@ -55,14 +55,16 @@ class l0_opts(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
                 ("x_init", ctypes.c_void_p), ("trace", ctypes.c_void_p),
-                ("tsize", ctypes.c_void_p), ("timeline", ctypes.c_void_p)]
+                ("tsize", ctypes.c_void_p), ("timeline", ctypes.c_void_p),
+                ("weights", ctypes.c_void_p)]
 
 
 class l0_problem(ctypes.Structure):
     _fields_ = [("col_idx", ctypes.c_void_p), ("n", ctypes.c_int64), ("m", ctypes.c_int32),
                 ("d", ctypes.c_int32), ("y", ctypes.c_void_p), ("alpha", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("x_out", ctypes.c_void_p)]
+                ("tol", ctypes.c_double), ("x_out", ctypes.c_void_p),
+                ("weights", ctypes.c_void_p)]
 
 
 class l0_batch_opts(ctypes.Structure):
@@ -162,11 +164,12 @@ def l0_workspace_bytes(n, m, d, max_iter) -> int:
     return lib().l0_workspace_bytes(n, m, d, max_iter)
 
 
-def _opts(rule, tol_mode, x_init, trace, tsize, timeline=None):
+def _opts(rule, tol_mode, x_init, trace, tsize, timeline=None, weights=None):
     return l0_opts(rule, tol_mode, 0, 0, None if x_init is None else x_init.data_ptr(),
                    None if trace is None else trace.data_ptr(),
                    None if tsize is None else tsize.data_ptr(),
-                   None if timeline is None else timeline.data_ptr())
+                   None if timeline is None else timeline.data_ptr(),
+                   None if weights is None else weights.data_ptr())
 
 
 def l0_decode_ex(col_idx, n, m, d, y, alpha, max_iter, tol, x_out, opts, res_out, workspace) -> int:
@@ -198,12 +201,14 @@ def l0_solve(h, y, alpha, max_iter, tol, x_out, opts, res_out, workspace) -> int
 
 def problem_table(problems):
     """A ctypes l0_problem array from dicts with keys col_idx, n, m, d, y,
-    alpha, max_iter, tol and x_out (tensors for the buffers)."""
+    alpha, max_iter, tol, x_out and optionally weights (tensors for the
+    buffers)."""
     arr = (l0_problem * len(problems))()
     for i, p in enumerate(problems):
+        w = p.get("weights")
         arr[i] = l0_problem(p["col_idx"].data_ptr(), p["n"], p["m"], p["d"], p["y"].data_ptr(),
                             float(p["alpha"]), p["max_iter"], 0, float(p["tol"]),
-                            p["x_out"].data_ptr())
+                            p["x_out"].data_ptr(), None if w is None else w.data_ptr())
     return arr
 
 
@@ -272,9 +277,11 @@ def new_result(device="cuda"):
 
 
 def decode(col_idx, y, n, m, d, alpha=None, *, max_iter=100, tol=1e-10, rule=L0_RULE_L0DEC,
-           tol_mode=L0_TOL_RELATIVE, x_init=None, want_trace=True):
-    """Decode y = A x on the GPU via l0_decode_ex; returns a dict with x (device
-    tensor), iters, outcome, final_nnz, support_size, updates, trace, tsize."""
+           tol_mode=L0_TOL_RELATIVE, x_init=None, weights=None, want_trace=True):
+    """Decode y = A x on the GPU via l0_decode_ex (column weights of a
+    column-scaled A in `weights`, a device float64 tensor, or None); returns a
+    dict with x (device tensor), iters, outcome, final_nnz, support_size,
+    updates, trace, tsize."""
     dev = y.device
     alpha = float(math.ceil(d / 2)) if alpha is None else float(alpha)
     x = torch.empty(n, dtype=torch.float64, device=dev)
@@ -282,7 +289,7 @@ def decode(col_idx, y, n, m, d, alpha=None, *, max_iter=100, tol=1e-10, rule=L0_
     tsize = torch.zeros(max(max_iter, 1), dtype=torch.int64, device=dev) if want_trace else None
     res = new_result(dev)
     ws = torch.empty(l0_workspace_bytes(n, m, d, max_iter), dtype=torch.uint8, device=dev)
-    o = _opts(rule, tol_mode, x_init, trace, tsize)
+    o = _opts(rule, tol_mode, x_init, trace, tsize, weights=weights)
     _check(l0_decode_ex(col_idx, n, m, d, y, alpha, max_iter, tol, x, o, res, ws), "l0_decode_ex")
     torch.cuda.current_stream().synchronize()
     return _result_dict(res, trace, tsize, x)
@@ -352,13 +359,14 @@ class Server:
         self._keep = {}
         self._buf = (l0_completion * 256)()
 
-    def submit(self, req_id, col_idx, y, n, m, d, x_out, alpha=None, max_iter=100, tol=1e-10):
+    def submit(self, req_id, col_idx, y, n, m, d, x_out, alpha=None, max_iter=100, tol=1e-10,
+               weights=None):
         alpha = float(max(math.ceil(d / 2), 2)) if alpha is None else float(alpha)
         prob = l0_problem(col_idx.data_ptr(), n, m, d, y.data_ptr(), alpha, max_iter, 0, float(tol),
-                          x_out.data_ptr())
+                          x_out.data_ptr(), None if weights is None else weights.data_ptr())
         st = l0_server_submit(self.handle, prob, req_id)
         if st == L0_OK:
-            self._keep[int(req_id)] = (col_idx, y, x_out)
+            self._keep[int(req_id)] = (col_idx, y, x_out, weights)
         return st
 
     def poll(self):
@@ -412,21 +420,21 @@ class Matrix:
 
     def solve_async(self, y, alpha, *, max_iter=100, tol=1e-10, rule=L0_RULE_L0DEC,
                     tol_mode=L0_TOL_RELATIVE, x=None, res=None, trace=None, tsize=None,
-                    x_init=None, workspace=None, timeline=None):
+                    x_init=None, workspace=None, timeline=None, weights=None):
         """Enqueue one solve on the current stream; returns (x, res)."""
         x = torch.empty(self.n, dtype=torch.float64, device=y.device) if x is None else x
         res = new_result(y.device) if res is None else res
         ws = self.workspace(max_iter) if workspace is None else workspace
-        o = _opts(rule, tol_mode, x_init, trace, tsize, timeline)
+        o = _opts(rule, tol_mode, x_init, trace, tsize, timeline, weights)
         _check(l0_solve(self.handle, y, alpha, max_iter, tol, x, o, res, ws), "l0_solve")
         return x, res
 
     def solve(self, y, alpha, *, max_iter=100, tol=1e-10, rule=L0_RULE_L0DEC,
-              tol_mode=L0_TOL_RELATIVE, x_init=None, want_trace=True):
+              tol_mode=L0_TOL_RELATIVE, x_init=None, weights=None, want_trace=True):
         trace = torch.full((max_iter + 1,), -1, dtype=torch.int32, device=y.device) if want_trace else None
         tsize = torch.zeros(max(max_iter, 1), dtype=torch.int64, device=y.device) if want_trace else None
         x, res = self.solve_async(y, alpha, max_iter=max_iter, tol=tol, rule=rule, tol_mode=tol_mode,
-                                  trace=trace, tsize=tsize, x_init=x_init)
+                                  trace=trace, tsize=tsize, x_init=x_init, weights=weights)
         torch.cuda.current_stream().synchronize()
         return _result_dict(res, trace, tsize, x)
 

@@ -156,6 +156,7 @@ l0_status run_solve(const l0::MatrixView& A, const double* y, double alpha, int3
     q.rule = opts ? opts->rule : L0_RULE_L0DEC;
     q.tol_mode = opts ? opts->tol_mode : L0_TOL_RELATIVE;
     q.x_init = opts ? opts->x_init : nullptr;
+    q.w = opts ? opts->weights : nullptr;
     q.x = x_out;
     q.trace = opts ? opts->trace : nullptr;
     q.tsize = opts ? opts->tsize : nullptr;
@@ -172,6 +173,7 @@ bool common_buffers_ok(int64_t n, int32_t m, int32_t max_iter, const double* y, 
     if (!buffer_ok(x_out, static_cast<size_t>(n) * sizeof(double))) return false;
     if (opts) {
         if (opts->x_init && !buffer_ok(opts->x_init, static_cast<size_t>(n) * sizeof(double))) return false;
+        if (opts->weights && !buffer_ok(opts->weights, static_cast<size_t>(n) * sizeof(double))) return false;
         if (opts->trace && !buffer_ok(opts->trace, (static_cast<size_t>(max_iter) + 1) * sizeof(int32_t)))
             return false;
         if (opts->tsize && max_iter > 0 &&
@@ -206,6 +208,7 @@ const char* l0_status_string(int32_t code) {
         case L0_DEV_BAD_INDEX: return "L0_DEV_BAD_INDEX";
         case L0_DEV_NONFINITE_Y: return "L0_DEV_NONFINITE_Y";
         case L0_DEV_ABORTED: return "L0_DEV_ABORTED";
+        case L0_DEV_BAD_WEIGHT: return "L0_DEV_BAD_WEIGHT";
         default: return "unknown";
     }
 }
@@ -378,6 +381,7 @@ bool problems_ok(const l0_problem* probs, int32_t count, BatchPlan& pl, bool buf
             if (!buffer_ok(P.col_idx, static_cast<size_t>(P.n) * P.d * sizeof(int32_t))) return false;
             if (!buffer_ok(P.y, static_cast<size_t>(P.m) * sizeof(double))) return false;
             if (!buffer_ok(P.x_out, static_cast<size_t>(P.n) * sizeof(double))) return false;
+            if (P.weights && !buffer_ok(P.weights, static_cast<size_t>(P.n) * sizeof(double))) return false;
         }
     }
     pl.order.resize(count);

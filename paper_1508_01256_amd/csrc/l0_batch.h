@@ -58,7 +58,7 @@ struct IterCounters {
 struct alignas(256) TeamCtl {
     int bar;      // team barrier arrivals (monotonic)
     int abort;    // a barrier wait timed out
-    int bad;      // 1: non-finite y, 2: row index out of range
+    int bad;      // input errors (kErr* bits)
     int nnz;      // ||y||_0
     unsigned long long ymax_bits;  // max |y_i| (bits of a non-negative double)
     int support;  // |support|

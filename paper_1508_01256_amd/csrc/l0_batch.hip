@@ -54,6 +54,7 @@ constexpr int kBatchQueue = 2048;
 struct BlockState {
     gptr<double> x;
     gptr<const double> y;
+    gptr<const double> w;     // column weights, or null for unit columns
     gptr<double> r;
     gptr<uint32_t> rword;
     gptr<uint32_t> member;
@@ -72,6 +73,7 @@ __device__ BlockState carve(char* base, const l0_problem& P) {
     BlockState s{};
     s.x = global(P.x_out);
     s.y = global(P.y);
+    s.w = P.weights ? global(P.weights) : nullptr;
     s.r = global(reinterpret_cast<double*>(base + lay.r));
     s.rword = global(reinterpret_cast<uint32_t*>(base + lay.rword));
     s.member = global(reinterpret_cast<uint32_t*>(base + lay.member));
@@ -292,10 +294,10 @@ __device__ void score_column(gptr<const int32_t> col_idx, const BlockState& s, i
     for (int t = 0; t < D; ++t) rows[t] = col_idx[j * D + t];
 #pragma unroll
     for (int t = 0; t < D; ++t) v[t] = s.r[rows[t]];
-    double w;
-    const bool sel = rule_is_shifted(rule) ? exact_score_shifted<D>(v, pos, tau, rule, a, w)
-                                           : exact_score<D>(v, tau, rule, a, w);
-    if (sel) apply_update<D>(s, &ring->tcount, &ctl->support, &ring->affc, j, w, rows);
+    double om;
+    const bool sel = rule_is_shifted(rule) ? exact_score_shifted<D>(v, pos, tau, rule, a, om)
+                                           : exact_score<D>(v, tau, rule, a, om);
+    if (sel) apply_update<D>(s, &ring->tcount, &ctl->support, &ring->affc, j, column_update(s, j, om), rows);
 }
 
 // The vote of one iteration for this member, with the exact scoring of the
@@ -378,8 +380,8 @@ __device__ void wg_sort(Ptr buf, int cnt) {
 // row_residual for one row with a long support list, computed by the whole
 // workgroup (every thread calls it; the result is valid in thread 0): the
 // list is sorted (in LDS when it fits, else in place) when it has unsorted
-// entries, then x_hat is gathered 512 entries at a time into LDS and thread
-// 0 adds them in ascending j from +0.0.
+// entries, then the column terms are gathered 512 entries at a time into LDS
+// and thread 0 adds them in ascending j from +0.0.
 __device__ double long_row_residual(const BlockState& s, const Lds& L, int i) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int cnt = s.slot_cnt[i];
@@ -403,7 +405,7 @@ __device__ double long_row_residual(const BlockState& s, const Lds& L, int i) {
     double sum = 0.0;
     for (int c0 = 0; c0 < cnt; c0 += 512) {
         const int len = min(512, cnt - c0);
-        for (int t = tid; t < len; t += nthr) xb[t] = s.x[in_lds ? sb[c0 + t] : list[c0 + t]];
+        for (int t = tid; t < len; t += nthr) xb[t] = column_term(s, in_lds ? sb[c0 + t] : list[c0 + t]);
         __syncthreads();
         if (tid == 0)
             for (int t = 0; t < len; ++t) sum += xb[t];
@@ -461,8 +463,13 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
     const int64_t gt = static_cast<int64_t>(rank) * nthr + tid, gstep = static_cast<int64_t>(tsize) * nthr;
 
     // --- init, split over the team: x_hat = 0, support bitmap, per-row
-    //     state, r = y; max |y| and non-finite y into the control block
-    for (int64_t j = gt; j < n; j += gstep) s.x[j] = 0.0;
+    //     state, r = y; max |y|, non-finite y and unusable column weights
+    //     into the control block
+    int bad_w = 0;
+    for (int64_t j = gt; j < n; j += gstep) {
+        s.x[j] = 0.0;
+        if (s.w && !weight_ok(s.w[j])) bad_w = 1;
+    }
     for (int64_t w = gt; w < ((n + 31) >> 5); w += gstep) s.member[w] = 0u;
     double lmax = 0.0;
     int bad = 0;
@@ -477,10 +484,12 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
     }
     lmax = wg_max(lmax, (lptr<double>)L.red);
     bad = wg_sum(bad, L.red);
+    bad_w = wg_sum(bad_w, L.red);
     if (tid == 0) {
         __hip_atomic_fetch_max(&tm.ctl->ymax_bits, static_cast<unsigned long long>(__double_as_longlong(lmax)),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (bad) __hip_atomic_fetch_or(&tm.ctl->bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int flags = (bad ? kErrNonfiniteY : 0) | (bad_w ? kErrBadWeight : 0);
+        if (flags) __hip_atomic_fetch_or(&tm.ctl->bad, flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     bool alive = team_sync(tm, L);
 
@@ -524,7 +533,7 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         __syncthreads();
     }
     bad_idx = wg_sum(bad_idx, L.red);
-    if (tid == 0 && bad_idx) __hip_atomic_fetch_or(&tm.ctl->bad, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0 && bad_idx) __hip_atomic_fetch_or(&tm.ctl->bad, kErrBadIndex, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tsize > 1) {
         alive = alive && team_sync(tm, L);
         if (alive && lead) {
@@ -546,8 +555,7 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
     const int flags = load_agent(&tm.ctl->bad);
     if (!alive || flags) {
         if (lead && tid == 0)
-            write_result(res, 0, !alive ? L0_DEV_ABORTED : ((flags & 2) ? L0_DEV_BAD_INDEX : L0_DEV_NONFINITE_Y), 0,
-                         0, 0);
+            write_result(res, 0, !alive ? L0_DEV_ABORTED : error_outcome(flags), 0, 0, 0);
         __syncthreads();
         return;
     }

@@ -22,6 +22,21 @@ __device__ __forceinline__ V fetch_add(Ptr p, V v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Column j's term in a residual row: x_hat_j, or the rounded product
+// w_j * x_hat_j on a column-scaled A (S provides x and w).
+template <class S>
+__device__ __forceinline__ double column_term(const S& p, int64_t j) {
+    const double xj = p.x[j];
+    return p.w ? p.w[j] * xj : xj;
+}
+
+// The update of column j that cancels residual value v: v, or v / w_j on a
+// column-scaled A (w_j > 0).
+template <class S>
+__device__ __forceinline__ double column_update(const S& p, int64_t j, double v) {
+    return p.w ? v / p.w[j] : v;
+}
+
 // Apply x_hat_j += w for a selected column j with rows rows[0..D): count it in
 // *tcount, enter j into the support (bitmap; on first entry append j to each
 // row's support list and count it in *support), and record every row it
@@ -50,9 +65,9 @@ __device__ void apply_update(const S& p, C tcount, C support, C affc, int64_t j,
     }
 }
 
-// r_i = y_i - (sum over the support columns of row i, ascending, of x_hat_j).
-// The row's list holds its support columns; entries appended since the last
-// visit are merged into the sorted prefix first.
+// r_i = y_i - (sum over the support columns of row i, ascending, of their
+// column terms).  The row's list holds its support columns; entries appended
+// since the last visit are merged into the sorted prefix first.
 template <class S>
 __device__ double row_residual(const S& p, int i) {
     const auto list = p.slots + p.row_off[i];
@@ -69,7 +84,7 @@ __device__ double row_residual(const S& p, int i) {
     }
     if (done != cnt) p.slot_sorted[i] = cnt;
     double s = 0.0;
-    for (int q = 0; q < cnt; ++q) s += p.x[list[q]];
+    for (int q = 0; q < cnt; ++q) s += column_term(p, list[q]);
     return p.y[i] - s;
 }
 
@@ -99,8 +114,8 @@ __device__ __forceinline__ void sort_network(int (&v)[N]) {
 
 // row_residual for a row whose support list holds cnt <= N entries (N a
 // power of two): the list is sorted in registers (and written back) when it
-// has unsorted entries, x_hat is gathered for all entries at once, and the
-// sum still runs in ascending j from +0.0.
+// has unsorted entries, the column terms are gathered for all entries at
+// once, and the sum still runs in ascending j from +0.0.
 template <int N, class S>
 __device__ double row_residual_short(const S& p, int i, int cnt) {
     const auto list = p.slots + p.row_off[i];
@@ -116,7 +131,7 @@ __device__ double row_residual_short(const S& p, int i, int cnt) {
     }
     double xv[N];
 #pragma unroll
-    for (int q = 0; q < N; ++q) xv[q] = q < cnt ? p.x[v[q]] : 0.0;
+    for (int q = 0; q < N; ++q) xv[q] = q < cnt ? column_term(p, v[q]) : 0.0;
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < N; ++q)

@@ -44,13 +44,27 @@ struct MatrixBuffers {
 };
 MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d);
 
+// Input errors found on the device, as bits of a flag word (several may be
+// found at once); the outcome reported is the first of: row index out of
+// range, non-finite y, column weight not positive and finite.
+constexpr int kErrNonfiniteY = 1;
+constexpr int kErrBadIndex = 2;
+constexpr int kErrBadWeight = 4;
+__host__ __device__ inline int error_outcome(int flags) {
+    return (flags & kErrBadIndex) ? L0_DEV_BAD_INDEX
+         : (flags & kErrNonfiniteY) ? L0_DEV_NONFINITE_Y : L0_DEV_BAD_WEIGHT;
+}
+
+// A usable column weight: positive and finite.
+__host__ __device__ inline bool weight_ok(double w) { return w > 0.0 && w <= 1.7976931348623157e308; }
+
 // Control block at the start of the solve workspace (zeroed before each solve).
 constexpr int kMaxXcc = 16;     // XCDs (accelerator complex dies) a device may have
 constexpr int kXccStride = 32;  // per-XCD counters sit 128 bytes apart
 struct Ctrl {
     unsigned int bar;        // grid barrier: arrivals of per-XCD leaders (monotonic)
     int abort;               // set when a barrier timed out
-    int err;                 // device-detected error outcome, 0 if none
+    int err;                 // device-detected input errors (kErr* bits), 0 if none
     int nnz;                 // running ||r||_0
     unsigned long long maxabs_bits; // bits of max_i |y_i| (non-negative doubles order as integers)
     int support;             // columns ever updated
@@ -86,6 +100,7 @@ struct SolveParams {
     int32_t rule;
     int32_t tol_mode;
     const double* x_init;
+    const double* w;     // column weights of a column-scaled A, or nullptr
     // outputs
     double* x;
     int32_t* trace;

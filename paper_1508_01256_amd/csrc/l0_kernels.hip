@@ -182,10 +182,10 @@ __device__ void score_exact(const SolveParams& p, int l, int64_t j, double tau, 
     double v[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) v[t] = p.r[rows[t]];
-    double w;
-    const bool sel = rule_is_shifted(p.rule) ? exact_score_shifted<D>(v, pos, tau, p.rule, p.a, w)
-                                             : exact_score<D>(v, tau, p.rule, p.a, w);
-    if (sel) apply_update<D>(p, &p.tcount[l], &p.ctrl->support, &p.affc[l], j, w, rows);
+    double om;
+    const bool sel = rule_is_shifted(p.rule) ? exact_score_shifted<D>(v, pos, tau, p.rule, p.a, om)
+                                             : exact_score<D>(v, tau, p.rule, p.a, om);
+    if (sel) apply_update<D>(p, &p.tcount[l], &p.ctrl->support, &p.affc[l], j, column_update(p, j, om), rows);
 }
 
 constexpr int kQueue = 2048;  // per-workgroup queue of columns passing the filter
@@ -316,9 +316,15 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         return;
     }
 
-    // --- init: x_hat, support bitmap, per-row state, max |y|, finiteness
+    // --- init: x_hat, support bitmap, per-row state, max |y|, finiteness of
+    //     y, usable column weights
     {
-        for (int64_t j = gtid; j < p.n; j += gsize) p.x[j] = p.x_init ? p.x_init[j] : 0.0;
+        int bad_w = 0;
+        for (int64_t j = gtid; j < p.n; j += gsize) {
+            p.x[j] = p.x_init ? p.x_init[j] : 0.0;
+            if (p.w && !weight_ok(p.w[j])) bad_w = 1;
+        }
+        if (wave_count(bad_w != 0) && (tid & 63) == 0) atomicOr(&c->err, kErrBadWeight);
         const int64_t nwords = (p.n + 31) >> 5;
         for (int64_t w = gtid; w < nwords; w += gsize) p.member[w] = 0u;
         double lmax = 0.0;
@@ -336,8 +342,8 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         if ((tid & 63) == 0 && lmax > 0.0)
             atomicMax(reinterpret_cast<unsigned long long*>(&c->maxabs_bits),
                       static_cast<unsigned long long>(__double_as_longlong(lmax)));
-        if (wave_count(bad != 0) && (tid & 63) == 0) atomicExch(&c->err, L0_DEV_NONFINITE_Y);
-        if (gtid == 0 && *p.bad_index) atomicExch(&c->err, L0_DEV_BAD_INDEX);
+        if (wave_count(bad != 0) && (tid & 63) == 0) atomicOr(&c->err, kErrNonfiniteY);
+        if (gtid == 0 && *p.bad_index) atomicOr(&c->err, kErrBadIndex);
     }
     if (!grid_sync(c, site, limit, p.timeline)) {
         if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
@@ -345,7 +351,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     }
     const int err = ld_relaxed(&c->err);
     if (err) {
-        if (gtid == 0) write_result(p, 0, err, 0, 0, 0);
+        if (gtid == 0) write_result(p, 0, error_outcome(err), 0, 0, 0);
         return;
     }
     const double ymax = __longlong_as_double(static_cast<long long>(

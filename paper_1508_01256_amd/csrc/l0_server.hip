@@ -54,7 +54,6 @@ struct Slot {
     l0_status status = L0_OK;
 };
 
-size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
 
@@ -265,7 +264,8 @@ l0_status l0_server_submit(l0_server s, const l0_problem* prob, int64_t id) {
     if (one == 0) return L0_ERR_ARG;
     if (!l0::device_buffer_ok(prob->col_idx, static_cast<size_t>(prob->n) * prob->d * sizeof(int32_t)) ||
         !l0::device_buffer_ok(prob->y, static_cast<size_t>(prob->m) * sizeof(double)) ||
-        !l0::device_buffer_ok(prob->x_out, static_cast<size_t>(prob->n) * sizeof(double)))
+        !l0::device_buffer_ok(prob->x_out, static_cast<size_t>(prob->n) * sizeof(double)) ||
+        (prob->weights && !l0::device_buffer_ok(prob->weights, static_cast<size_t>(prob->n) * sizeof(double))))
         return L0_ERR_ARG;
     if (one > s->opts.budget_bytes) return L0_ERR_WORKSPACE;
     std::lock_guard<std::mutex> lock(s->mu);

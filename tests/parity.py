@@ -21,12 +21,13 @@ def to_dev(a, dtype):
 
 
 def gpu_run(n, m, d, col, y, alpha, *, max_iter=100, tol=1e-10, rule=l0.L0_RULE_L0DEC,
-            x_init=None, tol_mode=l0.L0_TOL_RELATIVE):
+            x_init=None, tol_mode=l0.L0_TOL_RELATIVE, w=None):
     colt = to_dev(col, torch.int32)
     yt = to_dev(y, torch.float64)
     xi = None if x_init is None else to_dev(x_init, torch.float64)
+    wt = None if w is None else to_dev(w, torch.float64)
     out = l0.decode(colt, yt, n, m, d, alpha, max_iter=max_iter, tol=tol, rule=rule, x_init=xi,
-                    tol_mode=tol_mode)
+                    tol_mode=tol_mode, weights=wt)
     out["x"] = out["x"].cpu().numpy()
     if "trace" in out:
         out["trace"] = out["trace"].numpy()
@@ -35,14 +36,14 @@ def gpu_run(n, m, d, col, y, alpha, *, max_iter=100, tol=1e-10, rule=l0.L0_RULE_
 
 
 def oracle_run(n, m, d, col, y, alpha, *, max_iter=100, tol=1e-10, rule=l0.L0_RULE_L0DEC,
-               x_init=None, tol_mode=l0.L0_TOL_RELATIVE):
+               x_init=None, tol_mode=l0.L0_TOL_RELATIVE, w=None):
     if tol_mode == l0.L0_TOL_ABSOLUTE:
         # the oracle takes a relative tolerance; convert (exact only when the
         # division and multiplication round-trip, so tests use powers of two)
         s = float(np.max(np.abs(y)))
         tol = tol / s if s > 0 else tol
     return oracle.parallel_l0(n, m, d, col, y, alpha, max_iter=max_iter, tol=tol,
-                              rule=RULE_MAP[rule], x_init=x_init)
+                              rule=RULE_MAP[rule], x_init=x_init, w=w)
 
 
 def assert_parity(g, o, *, label=""):
@@ -61,9 +62,13 @@ def assert_parity(g, o, *, label=""):
 
 
 def run_both(inst_or_arrays, **kw):
+    """GPU and oracle runs of one instance; an Instance with column weights
+    is decoded with them (unless w= is given)."""
     if hasattr(inst_or_arrays, "col_idx"):
         i = inst_or_arrays
         args = (i.n, i.m, i.d, i.col_idx, i.y, kw.pop("alpha", i.alpha))
+        if i.w is not None:
+            kw.setdefault("w", i.w)
     else:
         args = inst_or_arrays
     g = gpu_run(*args, **kw)
@@ -74,14 +79,17 @@ def run_both(inst_or_arrays, **kw):
 def batched_run(insts, *, alphas=None, max_iters=None, tol=1e-10, rule=l0.L0_RULE_L0DEC,
                 tol_mode=l0.L0_TOL_RELATIVE, block_threads=0, words_cap=0, autotune=False):
     """Decode Instances (or (n, m, d, col, y, alpha) tuples) in one
-    l0_decode_batched call; returns one dict per instance (x as numpy)."""
+    l0_decode_batched call, with each Instance's column weights when it has
+    them; returns one dict per instance (x as numpy)."""
     probs = []
     for q, i in enumerate(insts):
         n, m, d, col, y, a = (i.n, i.m, i.d, i.col_idx, i.y, i.alpha) if hasattr(i, "col_idx") else i
+        w = getattr(i, "w", None)
         probs.append(dict(col_idx=to_dev(col, torch.int32), n=n, m=m, d=d,
                           y=to_dev(y, torch.float64),
                           alpha=a if alphas is None else alphas[q],
-                          max_iter=100 if max_iters is None else max_iters[q], tol=tol))
+                          max_iter=100 if max_iters is None else max_iters[q], tol=tol,
+                          weights=None if w is None else to_dev(w, torch.float64)))
     xs, res = l0.decode_batched(probs, rule=rule, tol_mode=tol_mode, block_threads=block_threads,
                                 words_cap=words_cap, autotune=autotune)
     for x, r in zip(xs, res):

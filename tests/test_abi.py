@@ -86,6 +86,7 @@ def test_bad_options_and_handles():
 def test_status_strings():
     assert "CONVERGED" in l0.l0_status_string(0)
     assert l0.l0_status_string(l0.L0_DEV_BAD_INDEX) == "L0_DEV_BAD_INDEX"
+    assert l0.l0_status_string(l0.L0_DEV_BAD_WEIGHT) == "L0_DEV_BAD_WEIGHT"
 
 
 def _table(**over):
@@ -144,7 +145,8 @@ def test_struct_layouts_match_the_header(tmp_path):
         '  printf("l0_result %zu\\n", sizeof(l0_result));\n'
         '  F(l0_problem, n) F(l0_problem, m) F(l0_problem, d) F(l0_problem, y) F(l0_problem, alpha)\n'
         '  F(l0_problem, max_iter) F(l0_problem, tol) F(l0_problem, x_out)\n'
-        '  F(l0_opts, x_init) F(l0_opts, timeline) F(l0_batch_opts, words_cap)\n'
+        '  F(l0_opts, x_init) F(l0_opts, timeline) F(l0_opts, weights) F(l0_batch_opts, words_cap)\n'
+        '  F(l0_problem, weights)\n'
         '  F(l0_batch_opts, timing)\n'
         '  printf("l0_server_opts %zu\\n", sizeof(l0_server_opts));\n'
         '  printf("l0_completion %zu\\n", sizeof(l0_completion));\n'
@@ -178,6 +180,7 @@ def test_struct_layouts_match_the_header(tmp_path):
             if key in got:
                 assert got[key] == getattr(cls, f).offset, key
     assert got["l0_result.updates"] == 16
+    assert got["l0_opts.weights"] == 48 and got["l0_problem.weights"] == 64
 
 
 def test_server_argument_errors():

@@ -7,7 +7,7 @@ import torch
 
 import gen
 import paper_1508_01256_amd as l0
-from parity import assert_batched_parity, batched_run, gpu_run, oracle_run, say
+from parity import assert_batched_parity, batched_run, gpu_run, oracle_run, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -19,9 +19,11 @@ def _gpu():
     l0.lib()
 
 
-def sweep_like(count, seed, n_max_log2=14):
+def sweep_like(count, seed, n_max_log2=14, scaled=None):
     """Instances shaped like the phase-transition sweep (mixed n, delta, d
-    in {5, 7, 9}, rho), with n capped so the oracle finishes in seconds."""
+    in {5, 7, 9}, rho), with n capped so the oracle finishes in seconds.
+    scaled: None (unit columns), "all" or "half" (every other instance draws
+    +-1 nonzeros on a column-scaled A)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for i in range(count):
@@ -30,7 +32,9 @@ def sweep_like(count, seed, n_max_log2=14):
         d = int(rng.choice([5, 7, 9]))
         m = max(gen.mk_m(n, delta), d)
         k = gen.mk_k(m, float(rng.uniform(0.05, 0.5)))
-        out.append(gen.make_instance(seed * 7919 + i, n, m, d, k))
+        sc = scaled == "all" or (scaled == "half" and i % 2 == 0)
+        out.append(gen.make_instance(seed * 7919 + i, n, m, d, k, scaled=sc,
+                                     kind=gen.VALUES_PM1 if sc else gen.VALUES_NORMAL))
     return out
 
 
@@ -38,7 +42,7 @@ def check_all(insts, res, label, **kw):
     for q, (i, b) in enumerate(zip(insts, res)):
         o = oracle_run(i.n, i.m, i.d, i.col_idx, i.y, kw.get("alphas", [i.alpha] * len(insts))[q],
                        max_iter=kw.get("max_iters", [100] * len(insts))[q],
-                       rule=kw.get("rule", l0.L0_RULE_L0DEC))
+                       rule=kw.get("rule", l0.L0_RULE_L0DEC), w=i.w)
         assert_batched_parity(b, o, label=f"{label}/{q} n={i.n} m={i.m} d={i.d} k={i.k}")
 
 
@@ -215,3 +219,46 @@ def test_shifted_rules_in_a_batch(rule):
     alphas = [2.0 if q % 2 else float(i.alpha) for q, i in enumerate(insts)]
     res = batched_run(insts, alphas=alphas, rule=rule)
     check_all(insts, res, f"shifted{rule}", alphas=alphas, rule=rule)
+
+
+@pytest.mark.parametrize("rule", [l0.L0_RULE_L0DEC, l0.L0_RULE_SHIFTED_L0DEC])
+def test_column_scaled_instances_in_a_batch(rule):
+    """Column-scaled A (Section 4.3.3) per instance: a batch mixing +-1
+    signals on scaled columns with unit-column instances, including
+    team-decoded ones with words in LDS and in global memory; each against
+    the oracle and against its solo run."""
+    big = [gen.make_instance(48, 1 << 20, 104858, 7, 9000, kind=gen.VALUES_PM1, scaled=True),
+           gen.make_instance(49, 400000, 8000, 7, 1500, kind=gen.VALUES_PM1, scaled=True)]
+    insts = big + sweep_like(50, 33, n_max_log2=13, scaled="half")
+    say("scaled batch", rule)
+    res = batched_run(insts, rule=rule, block_threads=512, words_cap=32768)
+    check_all(insts, res, f"scaled{rule}", rule=rule)
+    for q, i in enumerate(insts[:6]):
+        g = gpu_run(i.n, i.m, i.d, i.col_idx, i.y, i.alpha, rule=rule, w=i.w)
+        for key in ("iters", "outcome", "final_nnz", "support_size", "updates"):
+            assert res[q][key] == g[key], (q, key)
+        assert np.array_equal(res[q]["x"].view(np.int64), g["x"].view(np.int64)), q
+    # the scaled +-1 instances the oracle recovers are recovered exactly
+    assert res[0]["outcome"] == l0.L0_CONVERGED
+
+
+def test_bad_weight_fails_only_its_instance():
+    insts = sweep_like(10, 34, n_max_log2=12, scaled="all")
+    w3, w6 = insts[3].w.copy(), insts[6].w.copy()
+    w3[2] = 0.0
+    w6[insts[6].n - 1] = np.inf
+    probs = []
+    for q, i in enumerate(insts):
+        w = w3 if q == 3 else w6 if q == 6 else i.w
+        probs.append(dict(col_idx=to_dev(i.col_idx, torch.int32), n=i.n, m=i.m, d=i.d,
+                          y=to_dev(i.y, torch.float64), alpha=i.alpha, max_iter=100, tol=1e-10,
+                          weights=to_dev(w, torch.float64)))
+    xs, res = l0.decode_batched(probs)
+    assert res[3]["outcome"] == l0.L0_DEV_BAD_WEIGHT and not torch.any(xs[3])
+    assert res[6]["outcome"] == l0.L0_DEV_BAD_WEIGHT
+    for q, i in enumerate(insts):
+        if q in (3, 6):
+            continue
+        o = oracle_run(i.n, i.m, i.d, i.col_idx, i.y, i.alpha, w=i.w)
+        res[q]["x"] = xs[q].cpu().numpy()
+        assert_batched_parity(res[q], o, label=f"badw/{q}")

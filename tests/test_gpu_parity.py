@@ -29,8 +29,10 @@ def _gpu():
 def test_worked_cases(case):
     name, g_, y, x, c = case
     n, m, d, col = graph_arrays(g_)
+    w = np.array(g_["w"], float) if "w" in g_ else None
     say("worked", name, c)
-    g = gpu_run(n, m, d, col, y, c["alpha"], max_iter=c["max_iter"], tol=c["tol"], rule=RULES[c["rule"]])
+    g = gpu_run(n, m, d, col, y, c["alpha"], max_iter=c["max_iter"], tol=c["tol"], rule=RULES[c["rule"]],
+                w=w)
     assert g["outcome"] == OUT[c["outcome"]] and g["iters"] == c["iters"]
     assert g["trace"].tolist() == c["trace"] and g["tsize"].tolist() == c["tsize"]
     assert np.array_equal(g["x"], np.array(c["x_hat"], float))

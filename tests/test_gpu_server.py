@@ -35,7 +35,8 @@ def serve_like(count, seed, lo=10.0, hi=16.0):
 
 def upload(insts):
     return [dict(col=to_dev(i.col_idx, torch.int32), y=to_dev(i.y, torch.float64),
-                 x=torch.empty(i.n, dtype=torch.float64, device="cuda")) for i in insts]
+                 x=torch.empty(i.n, dtype=torch.float64, device="cuda"),
+                 w=None if i.w is None else to_dev(i.w, torch.float64)) for i in insts]
 
 
 def run_server(insts, bufs, *, budget=1 << 30, order=None, **kw):
@@ -43,7 +44,7 @@ def run_server(insts, bufs, *, budget=1 << 30, order=None, **kw):
     with l0.Server(budget, **kw) as srv:
         for q in (order if order is not None else range(len(insts))):
             i, b = insts[q], bufs[q]
-            assert srv.submit(q, b["col"], b["y"], i.n, i.m, i.d, b["x"], i.alpha) == l0.L0_OK
+            assert srv.submit(q, b["col"], b["y"], i.n, i.m, i.d, b["x"], i.alpha, weights=b["w"]) == l0.L0_OK
             for c in srv.poll():
                 done[c["id"]] = c
         for c in srv.drain():
@@ -58,7 +59,7 @@ def check_against_oracle(insts, bufs, done, label):
         c = done[q]
         assert c["status"] == l0.L0_OK, (label, q)
         assert c["submit_s"] <= c["launch_s"] <= c["done_s"], (label, q)
-        o = oracle_run(i.n, i.m, i.d, i.col_idx, i.y, i.alpha)
+        o = oracle_run(i.n, i.m, i.d, i.col_idx, i.y, i.alpha, w=i.w)
         x = bufs[q]["x"].cpu().numpy()
         assert c["outcome"] == o["outcome"] and c["iters"] == o["iters"], (label, q)
         assert c["final_nnz"] == int(o["trace"][-1]) and c["updates"] == int(np.sum(o["tsize"])), (label, q)
@@ -118,3 +119,15 @@ def test_large_requests_use_teams():
     bufs = upload(insts)
     done = run_server(insts, bufs, budget=4 << 30)
     check_against_oracle(insts, bufs, done, "teams")
+
+
+def test_column_scaled_requests():
+    """Requests on column-scaled matrices (+-1 signals), mixed with unit-column
+    ones: each against the oracle."""
+    plain = serve_like(16, 25)
+    scaled = [gen.make_instance(9000 + q, i.n, i.m, i.d, i.k, kind=gen.VALUES_PM1, scaled=True)
+              for q, i in enumerate(serve_like(16, 26))]
+    insts = [x for pair in zip(plain, scaled) for x in pair]
+    bufs = upload(insts)
+    done = run_server(insts, bufs, max_inflight=2)
+    check_against_oracle(insts, bufs, done, "scaled")
