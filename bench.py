@@ -23,6 +23,7 @@ on one full decode of the same instance.
 from __future__ import annotations
 
 import argparse
+from concurrent.futures import ThreadPoolExecutor
 import hashlib
 import json
 import os
@@ -92,10 +93,17 @@ def main():
     ap.add_argument("--repeats", type=int, default=30, help="l0_solve launches timed for the roofline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--kind", choices=["normal", "pm1"], default="normal")
-    ap.add_argument("--workload", choices=["single", "sweep", "serve"], default="single",
+    ap.add_argument("--workload", choices=["single", "sweep", "serve", "phase"], default="single",
                     help="single: one n=2^24 instance (default); sweep: 4096 phase-transition "
                          "instances through the batched decoder; serve: 2000 Poisson-arriving "
-                         "requests through the decoding server")
+                         "requests through the decoding server; phase: 50%% recovery curves "
+                         "rho*(delta) by the adaptive protocol of the paper's experiments")
+    ap.add_argument("--phase-n", type=int, default=1 << 18, help="phase: problem size n")
+    ap.add_argument("--phase-problems", type=int, default=10, help="phase: problems per (delta, rho)")
+    ap.add_argument("--phase-curves", default="all", help="phase: comma-separated curve names, or all")
+    ap.add_argument("--phase-check-every", type=int, default=400,
+                    help="phase: every this many decoded instances is also run through the oracle")
+    ap.add_argument("--phase-out", default="", help="phase: also write a markdown summary here")
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: server workspace budget")
     ap.add_argument("--sweep-count", type=int, default=4096)
@@ -106,8 +114,8 @@ def main():
                          "rocprofv3 byte counters, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the decoder has no "
-              "multi-GPU path in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the decoder runs on "
+              "one GPU", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -130,6 +138,8 @@ def main():
         return sweep(args)
     if args.workload == "serve":
         return serve(args)
+    if args.workload == "phase":
+        return phase(args)
     kind = gen.VALUES_NORMAL if args.kind == "normal" else gen.VALUES_PM1
     t0 = time.time()
     inst = gen.single_workload("n2^24", 0, kind=kind)
@@ -550,6 +560,262 @@ def serve(args):
         "detail": {"plain_capacity_per_s": round(capacity, 1), "runs": runs},
     }
     print(json.dumps(out), flush=True)
+
+
+# name -> (d, alpha, rule, values, scaled columns, band): the paper's protocol at its experimental
+# alpha = 2 with Algorithm 2's score, the frequency rule (parallel-LDDSR), the workloads' alpha =
+# ceil(d/2), the shifted rule, banded signals, other degrees, and +-1 signals on unit and on
+# column-scaled A.
+PHASE_CURVES = {
+    "l0dec-a2": (7, 2.0, "L0DEC", "normal", False, 0.0),
+    "mode-a2": (7, 2.0, "MODE", "normal", False, 0.0),
+    "l0dec-a4": (7, 4.0, "L0DEC", "normal", False, 0.0),
+    "shifted-a2": (7, 2.0, "SHIFTED_L0DEC", "normal", False, 0.0),
+    "band0.5-a2": (7, 2.0, "L0DEC", "normal", False, 0.5),
+    "band0.9-a2": (7, 2.0, "L0DEC", "normal", False, 0.9),
+    "d5-a2": (5, 2.0, "L0DEC", "normal", False, 0.0),
+    "d9-a2": (9, 2.0, "L0DEC", "normal", False, 0.0),
+    "d13-a2": (13, 2.0, "L0DEC", "normal", False, 0.0),
+    "d19-a2": (19, 2.0, "L0DEC", "normal", False, 0.0),
+    "pm1-a2": (7, 2.0, "L0DEC", "pm1", False, 0.0),
+    "pm1-scaled-a2": (7, 2.0, "L0DEC", "pm1", True, 0.0),
+}
+
+
+def phase_deltas():
+    """The delta grid of the paper's phase-transition protocol (Section 5.1):
+    0.02 p for p = 1..4, then 0.1 + 89 (p - 1) / 1900 for p = 1..20."""
+    return [0.02 * p for p in range(1, 5)] + [0.1 + 89.0 * (p - 1) / 1900.0 for p in range(1, 21)]
+
+
+def logistic_50(rhos, succ, total):
+    """50% point of a logistic fit p(rho) = 1 / (1 + exp((rho - rho_star) / s))
+    to success counts (binomial likelihood; a weak prior on log s keeps the
+    fit finite when successes and failures separate perfectly)."""
+    import numpy as np
+    from scipy.optimize import minimize
+
+    r = np.asarray(rhos, float)
+    k = np.asarray(succ, float)
+    t = np.asarray(total, float)
+    if k.sum() == 0:
+        return None
+    if k.sum() == t.sum():
+        return float(r.max())
+
+    def nll(th):
+        z = (r - th[0]) / np.exp(th[1])
+        # log p = -log(1 + e^z), log(1 - p) = z - log(1 + e^z)
+        lp = -np.logaddexp(0.0, z)
+        lq = z - np.logaddexp(0.0, z)
+        return -(k * lp + (t - k) * lq).sum() + 1e-3 * (th[1] - np.log(0.01)) ** 2
+
+    mid = float(np.sum(r * k) / np.sum(k))
+    best = min((minimize(nll, np.array([x0, np.log(0.01)]), method="Nelder-Mead",
+                         options={"xatol": 1e-7, "fatol": 1e-10, "maxiter": 4000})
+                for x0 in (mid, float(r[k > 0].max()))), key=lambda o: o.fun)
+    return float(best.x[0])
+
+
+def phase_protocol(curve, n, problems, decode, log, check_every=0, start=0):
+    """Run the adaptive protocol for one curve: for each delta start at
+    rho = 0.01 with `problems` instances; while at least one is recovered,
+    raise rho by 0.01.  decode(insts, alpha, rule, keep) returns per instance
+    (outcome, iters, relative error ||x_hat - x||_inf / ||x||_inf, x_hat or
+    None), x_hat on the host where keep is set.  Every check_every-th decoded
+    instance (counting from `start` over all curves) is kept.  Returns per
+    delta the (rho, successes) points, the kept records and the count of
+    instances decoded."""
+    import numpy as np
+
+    import gen
+
+    d, alpha, rule, kind, scaled, band = PHASE_CURVES[curve]
+    deltas = phase_deltas()
+    mats = {}
+
+    def matrix(di, q):
+        key = (di, q)
+        if key not in mats:
+            m = int(round(deltas[di] * n))
+            seed = gen.SEED + 5000 + 100000 * d + 100 * di + q
+            mats[key] = (m, seed, gen.columns(seed, n, m, d), gen.weights(seed, n) if scaled else None)
+        return mats[key]
+
+    points = {di: [] for di in range(len(deltas))}
+    active = list(range(len(deltas)))
+    step = 0
+    records = []
+    len_done = 0
+    while active:
+        rho = round(0.01 * (step + 1), 2)
+        def draw(di, q):
+            m, seed, col, w = matrix(di, q)
+            k = min(int(np.floor(rho * m + 1e-9)), n)
+            sseed = seed * 1009 + step
+            supp = gen.support(sseed, n, k)
+            if kind == "pm1":
+                vals = gen.values(sseed, supp, gen.VALUES_PM1)
+            else:
+                vals = gen.banded_values(sseed, supp, band)
+            y = gen.measure(n, m, d, col, supp, vals, w)
+            return gen.Instance(n, m, d, k, sseed, col, supp, vals, y, alpha,
+                                gen.VALUES_PM1 if kind == "pm1" else gen.VALUES_NORMAL, w)
+
+        for di in active:  # matrices first (cached), then the signals in parallel
+            for q in range(problems):
+                matrix(di, q)
+        with ThreadPoolExecutor(8) as pool:
+            insts = list(pool.map(lambda a: draw(*a), [(di, q) for di in active for q in range(problems)]))
+        keep = [check_every > 0 and (start + len_done + q) % check_every == 0 for q in range(len(insts))]
+        outs = decode(insts, alpha, rule, keep)
+        len_done += len(insts)
+        nxt = []
+        for a, di in enumerate(active):
+            ok = 0
+            for q in range(problems):
+                inst = insts[a * problems + q]
+                oc, it, err, x = outs[a * problems + q]
+                ok += int(oc == 0 and err <= 1e-6)
+                if x is not None:
+                    records.append((curve, di, rho, inst, oc, it, x))
+            points[di].append((rho, ok))
+            if ok > 0 and rho < 1.0 - 1e-9:
+                nxt.append(di)
+        log(f"[phase] {curve}: rho={rho:.2f} active deltas {len(active)} -> {len(nxt)}")
+        active = nxt
+        step += 1
+    return deltas, points, records, len_done
+
+
+def phase(args):
+    """Phase transitions (Section 5.1 protocol; bands of Section 5.6; degrees
+    of Section 5.7) decoded by the batched decoder, one l0_decode_batched
+    call per curve and rho step, with sampled instances checked bitwise
+    against the oracle."""
+    import numpy as np
+    import torch
+
+    import paper_1508_01256_amd as l0
+
+    names = list(PHASE_CURVES) if args.phase_curves == "all" else args.phase_curves.split(",")
+    for c in names:
+        if c not in PHASE_CURVES:
+            raise SystemExit(f"unknown curve {c}; known: {', '.join(PHASE_CURVES)}")
+    rules = {"L0DEC": l0.L0_RULE_L0DEC, "MODE": l0.L0_RULE_MODE, "SHIFTED_L0DEC": l0.L0_RULE_SHIFTED_L0DEC}
+    dev = "cuda"
+    gpu_ms = [0.0]
+    solves = [0]
+
+    cache = {}  # host array id -> device copy (matrices and weights stay resident per curve)
+
+    def resident(a):
+        t = cache.get(id(a))
+        if t is None or t[0] is not a:
+            t = (a, torch.from_numpy(a).to(dev))
+            cache[id(a)] = t
+        return t[1]
+
+    def decode(insts, alpha, rule, keep):
+        probs = [dict(col_idx=resident(i.col_idx), n=i.n, m=i.m, d=i.d,
+                      y=torch.from_numpy(i.y).to(dev), alpha=alpha, max_iter=100, tol=1e-10,
+                      x_out=torch.empty(i.n, dtype=torch.float64, device=dev),
+                      weights=None if i.w is None else resident(i.w)) for i in insts]
+        table = l0.problem_table(probs)
+        # the largest LDS word capacity whose schedule fits this degree
+        for bt, wc in ((512, 32768), (512, 16384), (256, 8192)):
+            opts = l0.l0_batch_opts(rules[rule], 0, bt, wc)
+            nb = l0.l0_batch_workspace_bytes(table, opts)
+            if nb:
+                break
+        results = l0.new_results(len(probs), dev)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st = l0.l0_decode_batched(table, opts, results, ws)
+        e1.record(stream)
+        if st != l0.L0_OK:
+            raise RuntimeError(f"l0_decode_batched status {st}")
+        torch.cuda.synchronize()
+        gpu_ms[0] += e0.elapsed_time(e1)
+        solves[0] += len(probs)
+        rl = l0.results_list(results)
+        out = []
+        for i, r, p, kp in zip(insts, rl, probs, keep):
+            xt = torch.zeros(i.n, dtype=torch.float64, device=dev)
+            if i.k:
+                xt[torch.from_numpy(i.supp).to(dev)] = torch.from_numpy(i.vals).to(dev)
+            err = float((p["x_out"] - xt).abs().max()) / (float(np.max(np.abs(i.vals))) if i.k else 1.0)
+            out.append((r["outcome"], r["iters"], err, p["x_out"].cpu().numpy() if kp else None))
+        return out
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    import oracle
+    t0 = time.time()
+    curves = {}
+    checked = agree = 0
+    cdt = 0.0
+    seen = 0
+    for c in names:
+        cache.clear()
+        deltas, points, records, count = phase_protocol(c, args.phase_n, args.phase_problems, decode, log,
+                                                        args.phase_check_every, seen)
+        seen += count
+        d, alpha, rule, kind, scaled, band = PHASE_CURVES[c]
+        star = {}
+        for di, pts in points.items():
+            rs = [r for r, _ in pts]
+            ks = [k for _, k in pts]
+            star[round(deltas[di], 4)] = logistic_50(rs, ks, [args.phase_problems] * len(rs))
+        curves[c] = star
+        orule = {"L0DEC": oracle.RULE_L0DEC, "MODE": oracle.RULE_MODE,
+                 "SHIFTED_L0DEC": oracle.RULE_SHIFTED_L0DEC}[rule]
+        for (_, di, rho, inst, oc, it, x) in records:
+            c0 = time.perf_counter()
+            o = oracle.parallel_l0(inst.n, inst.m, inst.d, inst.col_idx, inst.y, alpha, max_iter=100,
+                                   tol=1e-10, rule=orule, w=inst.w)
+            cdt += time.perf_counter() - c0
+            checked += 1
+            agree += int(o["outcome"] == oc and o["iters"] == it and np.array_equal(o["x"], x))
+        log(f"[phase] {c}: rho*(delta) = " + ", ".join(
+            f"{dl:.3f}:{'-' if v is None else f'{v:.3f}'}" for dl, v in star.items()))
+    wall = time.time() - t0
+    log(f"[phase] {solves[0]} solves, GPU {gpu_ms[0] / 1e3:.2f} s, wall {wall:.1f} s; "
+        f"oracle agreement {agree}/{checked}")
+    cpu = None
+    if not args.no_cpu and checked:
+        cpu = {"value": round(checked / cdt, 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{checked} instances (every {args.phase_check_every}th decoded), {cdt:.1f} s "
+                         f"single thread; {agree}/{checked} bitwise equal to the batched GPU results"}
+    out = {
+        "metric": "phase transitions: 50% recovery rho*(delta) by logistic fit, batched decoder",
+        "value": round(solves[0] / (gpu_ms[0] * 1e-3), 1), "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(gpu_ms[0], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"n={args.phase_n}, delta grid of 24 values, rho from 0.01 in steps of "
+                               f"0.01 while any of {args.phase_problems} problems is recovered; "
+                               "success = CONVERGED and ||x_hat - x||_inf <= 1e-6 ||x||_inf; "
+                               "tol=1e-10, max_iter=100",
+                   "curves": {c: dict(zip(("d", "alpha", "rule", "values", "scaled", "band"),
+                                          PHASE_CURVES[c])) for c in names}},
+        "roofline": None,
+        "cpu_baseline": cpu,
+        "detail": {"solves": solves[0], "gpu_s": round(gpu_ms[0] / 1e3, 3), "wall_s": round(wall, 1),
+                   "oracle_checked": checked, "oracle_agree": agree, "rho_star": curves},
+    }
+    print(json.dumps(out), flush=True)
+    if args.phase_out:
+        deltas = phase_deltas()
+        with open(args.phase_out, "w") as f:
+            f.write("| delta | " + " | ".join(names) + " |\n|---|" + "---|" * len(names) + "\n")
+            for dl in deltas:
+                key = round(dl, 4)
+                cells = [("-" if curves[c][key] is None else f"{curves[c][key]:.3f}") for c in names]
+                f.write(f"| {dl:.3f} | " + " | ".join(cells) + " |\n")
 
 
 if __name__ == "__main__":

@@ -104,6 +104,21 @@ def weights(seed: int, n: int, lo: float = 0.5, hi: float = 1.5) -> np.ndarray:
     return out
 
 
+def banded_values(seed: int, supp: np.ndarray, band: float) -> np.ndarray:
+    """float64[k]: N(0,1) nonzeros of which round(band * k), chosen uniformly
+    (seeded), all equal one shared N(0,1) draw (the banded signals of the
+    almost-dissociated experiments, Section 5)."""
+    vals = values(seed, supp, VALUES_NORMAL)
+    k = vals.size
+    kb = int(round(float(band) * k))
+    if kb:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        pick = rng.choice(k, kb, replace=False)
+        # the shared value: the N(0,1) draw of index 0 in a stream keyed apart
+        vals[pick] = values(seed ^ 0x5EED5EED, np.zeros(1, dtype=np.int64))[0]
+    return vals
+
+
 def measure(n: int, m: int, d: int, col_idx: np.ndarray, supp: np.ndarray,
             vals: np.ndarray, w: np.ndarray | None = None) -> np.ndarray:
     """float64[m]: y = A x, each y_i summed from +0.0 over ascending columns;

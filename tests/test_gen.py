@@ -122,3 +122,33 @@ def test_workload_shapes():
     assert {q["d"] for q in p} == {5, 7, 9}
     s = gen.serve_params(2000)
     assert all(q["k"] == math.floor(0.15 * q["m"] + 1e-9) for q in s)
+
+
+def test_weights_and_scaled_measure():
+    w = gen.weights(3, 5000)
+    assert w.min() >= 0.5 and w.max() <= 1.5 and abs(w.mean() - 1.0) < 0.02
+    assert np.array_equal(w, gen.weights(3, 5000)) and not np.array_equal(w, gen.weights(4, 5000))
+    assert np.array_equal(gen.weights(3, 7000)[:5000], w)  # per-column streams
+    n, m, d = 200, 40, 5
+    col = gen.columns(1, n, m, d)
+    supp = gen.support(1, n, 12)
+    vals = gen.values(1, supp)
+    w = gen.weights(1, n)
+    y = gen.measure(n, m, d, col, supp, vals, w)
+    A = brute.dense_matrix(n, m, d, col) * w[None, :]
+    x = np.zeros(n)
+    x[supp] = vals
+    assert np.max(np.abs(y - A @ x)) <= 1e-14
+    assert np.array_equal(gen.measure(n, m, d, col, supp, vals, np.ones(n)), gen.measure(n, m, d, col, supp, vals))
+
+
+@pytest.mark.parametrize("band", [0.0, 0.3, 0.9, 1.0])
+def test_banded_values(band):
+    supp = gen.support(9, 100000, 2000)
+    v = gen.banded_values(9, supp, band)
+    _, counts = np.unique(v, return_counts=True)
+    kb = int(round(band * supp.size))
+    assert counts.max() == max(kb, 1)
+    if band == 0.0:
+        assert np.array_equal(v, gen.values(9, supp))
+    assert np.array_equal(v, gen.banded_values(9, supp, band))
