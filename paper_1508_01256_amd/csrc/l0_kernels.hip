@@ -413,17 +413,23 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
 
         // vote on the same residual for every column
         if (COMPACT) {
-            // several loads in flight per thread before the LDS stores
+            // 16-byte loads (the word array is 256-byte aligned), four in
+            // flight per thread before the LDS stores: 64 KiB of words per
+            // round; the last m % 4 words one by one
+            const int m4 = p.m >> 2;
+            const uint4* src4 = reinterpret_cast<const uint4*>(p.rword);
+            uint4* dst4 = reinterpret_cast<uint4*>(lds_w);
             int i = tid;
-            for (; i + 3 * kBlock < p.m; i += 4 * kBlock) {
-                const uint32_t a0 = p.rword[i], a1 = p.rword[i + kBlock];
-                const uint32_t a2 = p.rword[i + 2 * kBlock], a3 = p.rword[i + 3 * kBlock];
-                lds_w[i] = a0;
-                lds_w[i + kBlock] = a1;
-                lds_w[i + 2 * kBlock] = a2;
-                lds_w[i + 3 * kBlock] = a3;
+            for (; i + 3 * kBlock < m4; i += 4 * kBlock) {
+                const uint4 a0 = src4[i], a1 = src4[i + kBlock];
+                const uint4 a2 = src4[i + 2 * kBlock], a3 = src4[i + 3 * kBlock];
+                dst4[i] = a0;
+                dst4[i + kBlock] = a1;
+                dst4[i + 2 * kBlock] = a2;
+                dst4[i + 3 * kBlock] = a3;
             }
-            for (; i < p.m; i += kBlock) lds_w[i] = p.rword[i];
+            for (; i < m4; i += kBlock) dst4[i] = src4[i];
+            for (int t = (m4 << 2) + tid; t < p.m; t += kBlock) lds_w[t] = p.rword[t];
             __syncthreads();
             if (p.timeline && blockIdx.x == 0 && tid == 0)
                 p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
@@ -498,72 +504,132 @@ __global__ void zero_ints(int32_t* p, int64_t count) {
 
 // Repack col_idx (each column's d rows contiguous) into the tiled neighbour
 // planes, check every row index, and count row degrees (LDS histogram when m
-// fits, else global atomics).  Each wave takes groups of 64 columns: it reads
-// the group's 64*D contiguous indices with coalesced loads into an LDS
-// staging area and writes each neighbour plane's 64 entries contiguously.
+// fits, else global atomics).  A group is 64 columns: their 64*D contiguous
+// indices arrive by D coalesced loads, go through the wave's LDS staging area
+// and leave as D contiguous 64-entry runs, one per neighbour plane.  Each wave
+// issues the loads of RepackGroups<D> consecutive groups before it stages the
+// first, so enough reads are in flight to stream at HBM rate; groups that lie
+// wholly inside the array are read from one base address (immediate offsets,
+// few address registers), only the last, partial one index by index.
 constexpr int kRepackWaves = 16;
-template <int D, typename IT>
-__global__ void __launch_bounds__(1024) repack_kernel(const int32_t* col_idx, MatrixView A, int lds_hist) {
+template <int D>
+struct RepackGroups {
+    static constexpr int value = D >= 28 ? 1 : 28 / D;
+};
+
+template <int D, typename IT, bool LDS_HIST>
+__global__ void __launch_bounds__(1024) repack_kernel(const int32_t* col_idx, MatrixView A) {
+    constexpr int G = RepackGroups<D>::value;
     extern __shared__ int sh[];
     int* hist = sh;
-    int* stage = sh + (lds_hist ? A.m : 0) + (threadIdx.x >> 6) * (64 * D);
+    int* stage = sh + (LDS_HIST ? A.m : 0) + (threadIdx.x >> 6) * (64 * D);
     const int lane = threadIdx.x & 63;
-    if (lds_hist)
+    if (LDS_HIST)
         for (int i = threadIdx.x; i < A.m; i += blockDim.x) hist[i] = 0;
     __syncthreads();
     const int64_t nd = A.n * D;
     const int64_t ngroups = A.ntiles * (kTile / 64);
+    const int64_t wave = static_cast<int64_t>(blockIdx.x) * kRepackWaves + (threadIdx.x >> 6);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kRepackWaves * G;
+    const unsigned m = static_cast<unsigned>(A.m);
     int bad = 0;
-    for (int64_t g = static_cast<int64_t>(blockIdx.x) * kRepackWaves + (threadIdx.x >> 6); g < ngroups;
-         g += static_cast<int64_t>(gridDim.x) * kRepackWaves) {
-        const int64_t e0 = g * 64 * D;
+    for (int64_t g0 = wave * G; g0 < ngroups; g0 += stride) {
+        int v[G][D];
+        if ((g0 + G) * 64 * D <= nd) {
+            const int32_t* base = col_idx + g0 * 64 * D + lane;
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int64_t e = e0 + k * 64 + lane;
-            int row = 0;
-            if (e < nd) {
-                row = __builtin_nontemporal_load(&col_idx[e]);
-                if (row < 0 || row >= A.m) {
-                    bad = 1;
-                    row = 0;
-                } else if (lds_hist) {
-                    atomicAdd(&hist[row], 1);
-                } else {
-                    atomicAdd(&A.deg[row], 1);
+            for (int gi = 0; gi < G; ++gi)
+#pragma unroll
+                for (int k = 0; k < D; ++k) v[gi][k] = __builtin_nontemporal_load(base + (gi * D + k) * 64);
+        } else {
+            // indices past the end read the last entry; their rows become 0
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi)
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const int64_t e = (g0 + gi) * 64 * D + k * 64 + lane;
+                    v[gi][k] = e < nd ? __builtin_nontemporal_load(&col_idx[e]) : 0;
                 }
-            }
-            stage[k * 64 + lane] = row;
         }
-        // the wave's LDS stores complete (lgkmcnt(0)) before any lane reads
-        // another lane's entries; the wave barrier keeps the compiler from
-        // moving the reads above
-        __builtin_amdgcn_s_waitcnt(0xC07F);
-        __builtin_amdgcn_wave_barrier();
-        const int64_t tile = g / (kTile / 64);
-        const int c = static_cast<int>(g % (kTile / 64)) * 64 + lane;
 #pragma unroll
-        for (int t = 0; t < D; ++t)
-            static_cast<IT*>(A.soa)[(tile * D + t) * kTile + c] = static_cast<IT>(stage[lane * D + t]);
+        for (int gi = 0; gi < G; ++gi) {
+            const int64_t g = g0 + gi;
+            if (g >= ngroups) break;
+            const int64_t e0 = g * 64 * D + lane;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int row = v[gi][k];
+                const bool inside = e0 + k * 64 < nd;
+                const bool ok = static_cast<unsigned>(row) < m;
+                bad |= inside && !ok;
+                if (inside && ok) {
+                    if (LDS_HIST) atomicAdd(&hist[row], 1);
+                    else atomicAdd(&A.deg[row], 1);
+                }
+                stage[k * 64 + lane] = inside && ok ? row : 0;
+            }
+            // the wave's LDS stores complete (lgkmcnt(0)) before any lane reads
+            // another lane's entries; the wave barrier keeps the compiler from
+            // moving the reads above
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            __builtin_amdgcn_wave_barrier();
+            const int64_t tile = g / (kTile / 64);
+            const int c = static_cast<int>(g % (kTile / 64)) * 64 + lane;
+            IT out[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) out[t] = static_cast<IT>(stage[lane * D + t]);
+            // every lane has read its entries before the next group's stores
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            __builtin_amdgcn_wave_barrier();
+            IT* dst = static_cast<IT*>(A.soa) + tile * D * kTile + c;
+#pragma unroll
+            for (int t = 0; t < D; ++t) dst[t * kTile] = out[t];
+        }
     }
     if (bad) atomicExch(A.bad_index, 1);
-    if (lds_hist) {
+    if (LDS_HIST) {
         __syncthreads();
         for (int i = threadIdx.x; i < A.m; i += blockDim.x)
             if (hist[i]) atomicAdd(&A.deg[i], hist[i]);
     }
 }
 
-// row_off = exclusive prefix sum of deg (one workgroup, chunks of 1024).
+// row_off = exclusive prefix sum of the row degrees (one workgroup), chunk by
+// chunk of kScanChunk rows staged in LDS: coalesced loads (kScanPer in flight
+// per thread), each thread scans kScanPer consecutive staged entries, the
+// workgroup scans the thread sums, coalesced stores.  The staging index is
+// padded by one word per 32 so that a wave's segment reads spread over the
+// LDS banks.
+constexpr int kScanPer = 12;
+constexpr int kScanChunk = 1024 * kScanPer;
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
+
 __global__ void __launch_bounds__(1024) scan_kernel(MatrixView A) {
+    __shared__ int s_val[kScanChunk + kScanChunk / 32];
     __shared__ int s_wave[16];
-    __shared__ int s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int base = 0; base < A.m; base += 1024) {
-        const int i = base + threadIdx.x;
-        const int v = i < A.m ? A.deg[i] : 0;
-        int incl = v;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int carry = 0;
+    for (int base = 0; base < A.m; base += kScanChunk) {
+        const int len = min(kScanChunk, A.m - base);
+        int v[kScanPer];
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) {
+            const int i = u * 1024 + tid;
+            v[u] = A.deg[base + (i < len ? i : len - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) {
+            const int i = u * 1024 + tid;
+            s_val[scan_pad(i)] = i < len ? v[u] : 0;
+        }
+        __syncthreads();
+        int sum = 0;
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) {
+            v[u] = s_val[scan_pad(tid * kScanPer + u)];
+            sum += v[u];
+        }
+        int incl = sum;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const int o = __shfl_up(incl, off);
@@ -571,15 +637,28 @@ __global__ void __launch_bounds__(1024) scan_kernel(MatrixView A) {
         }
         if (lane == 63) s_wave[wid] = incl;
         __syncthreads();
-        int before = 0;
-        for (int w = 0; w < wid; ++w) before += s_wave[w];
-        const int carry = s_carry;
-        if (i < A.m) A.row_off[i] = carry + before + incl - v;
+        int before = 0, total = 0;
+        for (int w = 0; w < 16; ++w) {
+            const int t = s_wave[w];
+            before += w < wid ? t : 0;
+            total += t;
+        }
+        int run = carry + before + incl - sum;
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) {
+            s_val[scan_pad(tid * kScanPer + u)] = run;
+            run += v[u];
+        }
         __syncthreads();
-        if (threadIdx.x == 1023) s_carry = carry + before + incl;
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) {
+            const int i = u * 1024 + tid;
+            if (i < len) A.row_off[base + i] = s_val[scan_pad(i)];
+        }
+        carry += total;
+        __syncthreads();  // s_val and s_wave are reused by the next chunk
     }
-    if (threadIdx.x == 0) A.row_off[A.m] = s_carry;
+    if (tid == 0) A.row_off[A.m] = carry;
 }
 
 // ---------------------------------------------------------------------------
@@ -614,14 +693,22 @@ uint64_t barrier_limit_ticks() {
 template <int D>
 hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s) {
     const int cus = device_cus();
-    hipLaunchKernelGGL(zero_ints, dim3(256), dim3(256), 0, s, A.deg, static_cast<int64_t>(A.m));
-    hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, A.bad_index, int64_t(1));
+    // the degree counts and the bad-index flag follow each other in the
+    // matrix buffers: one fill clears both
+    if (A.bad_index > A.deg) {
+        hipLaunchKernelGGL(zero_ints, dim3(256), dim3(256), 0, s, A.deg, static_cast<int64_t>(A.bad_index - A.deg) + 1);
+    } else {
+        hipLaunchKernelGGL(zero_ints, dim3(256), dim3(256), 0, s, A.deg, static_cast<int64_t>(A.m));
+        hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, A.bad_index, int64_t(1));
+    }
     const size_t hist_bytes = static_cast<size_t>(A.m) * sizeof(int);
     const size_t stage_bytes = static_cast<size_t>(kRepackWaves) * 64 * D * sizeof(int);
     const int lds_hist = hist_bytes + stage_bytes <= kLdsWordBytes ? 1 : 0;
     const size_t lds = (lds_hist ? hist_bytes : 0) + stage_bytes;
-    const void* fn = A.compact ? reinterpret_cast<const void*>(&repack_kernel<D, uint16_t>)
-                               : reinterpret_cast<const void*>(&repack_kernel<D, int32_t>);
+    const void* fn = A.compact ? (lds_hist ? reinterpret_cast<const void*>(&repack_kernel<D, uint16_t, true>)
+                                           : reinterpret_cast<const void*>(&repack_kernel<D, uint16_t, false>))
+                               : (lds_hist ? reinterpret_cast<const void*>(&repack_kernel<D, int32_t, true>)
+                                           : reinterpret_cast<const void*>(&repack_kernel<D, int32_t, false>));
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
@@ -631,12 +718,9 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s)
     const int64_t cap = static_cast<int64_t>(cus > 0 ? cus : 256) * (lds_hist ? 1 : 2);
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    if (A.compact)
-        hipLaunchKernelGGL((repack_kernel<D, uint16_t>), dim3(static_cast<unsigned>(blocks)), dim3(1024), lds, s,
-                           col_idx, A, lds_hist);
-    else
-        hipLaunchKernelGGL((repack_kernel<D, int32_t>), dim3(static_cast<unsigned>(blocks)), dim3(1024), lds, s,
-                           col_idx, A, lds_hist);
+    void* args[] = {const_cast<int32_t**>(&col_idx), const_cast<MatrixView*>(&A)};
+    hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(blocks)), dim3(1024), args, lds, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, A);
     return hipGetLastError();
 }
@@ -660,10 +744,18 @@ hipError_t solve_d(const SolveParams& p, hipStream_t s) {
     const int64_t want = (p.ntiles + kWaves - 1) / kWaves;
     if (grid > want) grid = want;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(zero_ints, dim3(1), dim3(256), 0, s, reinterpret_cast<int32_t*>(p.ctrl),
-                       static_cast<int64_t>(sizeof(Ctrl) / sizeof(int32_t)));
-    hipLaunchKernelGGL(zero_ints, dim3(8), dim3(256), 0, s, p.tcount,
-                       static_cast<int64_t>(4 * (p.max_iter + 2)));
+    // control block and per-iteration counters (adjacent in the workspace:
+    // one fill clears both)
+    int32_t* const ctrl_ints = reinterpret_cast<int32_t*>(p.ctrl);
+    if (p.tcount >= ctrl_ints + sizeof(Ctrl) / sizeof(int32_t) && p.tcount - ctrl_ints <= 4096) {
+        hipLaunchKernelGGL(zero_ints, dim3(8), dim3(256), 0, s, ctrl_ints,
+                           static_cast<int64_t>(p.tcount - ctrl_ints) + 4 * (p.max_iter + 2));
+    } else {
+        hipLaunchKernelGGL(zero_ints, dim3(1), dim3(256), 0, s, ctrl_ints,
+                           static_cast<int64_t>(sizeof(Ctrl) / sizeof(int32_t)));
+        hipLaunchKernelGGL(zero_ints, dim3(8), dim3(256), 0, s, p.tcount,
+                           static_cast<int64_t>(4 * (p.max_iter + 2)));
+    }
     SolveParams q = p;
     uint64_t limit = barrier_limit_ticks();
     void* args[] = {&q, &limit};
