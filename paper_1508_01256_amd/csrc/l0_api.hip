@@ -31,14 +31,13 @@ MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d) {
 SolveBuffers solve_layout(int64_t n, int32_t m, int32_t d, int32_t max_iter) {
     SolveBuffers b{};
     b.ctrl = align256(sizeof(Ctrl));
-    b.counters = align256(4 * (static_cast<size_t>(max_iter) + 2) * sizeof(int32_t));
+    b.counters = align256(2 * (static_cast<size_t>(max_iter) + 2) * sizeof(int32_t));
     b.r = align256(static_cast<size_t>(m) * sizeof(double));
     b.rword = align256(static_cast<size_t>(m) * sizeof(uint32_t));
     b.slot_cnt = b.slot_sorted = b.aff_flag = b.aff_list = align256(static_cast<size_t>(m) * sizeof(int32_t));
     b.member = align256(static_cast<size_t>((n + 31) / 32) * sizeof(uint32_t));
     b.slots = align256(static_cast<size_t>(n) * d * sizeof(int32_t));
-    b.overflow = align256(static_cast<size_t>(n) * sizeof(int32_t));
-    b.total = b.ctrl + b.counters + b.r + b.rword + 4 * b.slot_cnt + b.member + b.slots + b.overflow;
+    b.total = b.ctrl + b.counters + b.r + b.rword + 4 * b.slot_cnt + b.member + b.slots;
     return b;
 }
 
@@ -123,9 +122,7 @@ void carve_solve(l0::SolveParams& q, char* base, int64_t n, int32_t m, int32_t d
     char* p = base;
     q.ctrl = reinterpret_cast<l0::Ctrl*>(p);            p += b.ctrl;
     q.tcount = reinterpret_cast<int32_t*>(p);
-    q.affc = q.tcount + (max_iter + 2);
-    q.ovc = q.affc + (max_iter + 2);
-    q.vctr = q.ovc + (max_iter + 2);                     p += b.counters;
+    q.affc = q.tcount + (max_iter + 2);                  p += b.counters;
     q.r = reinterpret_cast<double*>(p);                  p += b.r;
     q.rword = reinterpret_cast<uint32_t*>(p);            p += b.rword;
     q.slot_cnt = reinterpret_cast<int32_t*>(p);          p += b.slot_cnt;
@@ -133,8 +130,7 @@ void carve_solve(l0::SolveParams& q, char* base, int64_t n, int32_t m, int32_t d
     q.aff_flag = reinterpret_cast<int32_t*>(p);          p += b.aff_flag;
     q.aff_list = reinterpret_cast<int32_t*>(p);          p += b.aff_list;
     q.member = reinterpret_cast<uint32_t*>(p);           p += b.member;
-    q.slots = reinterpret_cast<int32_t*>(p);              p += b.slots;
-    q.overflow = reinterpret_cast<int32_t*>(p);
+    q.slots = reinterpret_cast<int32_t*>(p);
 }
 
 l0_status run_solve(const l0::MatrixView& A, const double* y, double alpha, int32_t max_iter,

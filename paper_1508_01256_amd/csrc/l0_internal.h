@@ -78,8 +78,7 @@ struct Ctrl {
 };
 
 struct SolveBuffers {
-    size_t ctrl, counters, r, rword, slot_cnt, slot_sorted, aff_flag, aff_list, member, slots,
-        overflow, total;
+    size_t ctrl, counters, r, rword, slot_cnt, slot_sorted, aff_flag, aff_list, member, slots, total;
 };
 SolveBuffers solve_layout(int64_t n, int32_t m, int32_t d, int32_t max_iter);
 
@@ -112,8 +111,6 @@ struct SolveParams {
     Ctrl* ctrl;
     int32_t* tcount;     // int32[max_iter+2]
     int32_t* affc;       // int32[max_iter+2]
-    int32_t* ovc;        // int32[max_iter+2]: columns in the overflow queue per iteration
-    int32_t* vctr;       // int32[max_iter+2]: chunks claimed by the vote of each iteration
     double* r;
     uint32_t* rword;     // uint32[m]: bucket word of each residual entry
     int32_t* slot_cnt;
@@ -122,7 +119,6 @@ struct SolveParams {
     int32_t* aff_list;
     uint32_t* member;
     int32_t* slots;
-    int32_t* overflow;   // int32[n]: columns that passed the filter beyond the LDS queues
 };
 
 // Enqueue the matrix preparation (repack, range check, degree histogram, scan).

@@ -201,88 +201,122 @@ struct Chunk {
 
 template <int D, bool COMPACT>
 __device__ __forceinline__ void load_chunk(const void* soa, uint32_t g, uint32_t lane, uint32_t (&rows)[D]) {
-    const uint32_t* __restrict__ s32 = static_cast<const uint32_t*>(soa);
     constexpr uint32_t plane = COMPACT ? kTile / 2 : kTile;  // 32-bit words per plane of a tile
     constexpr uint32_t per = Chunk<COMPACT>::kPerTile;
-    const uint32_t base = (g / per) * (D * plane) + (g % per) * 64u + lane;
+    // one base address; the planes are immediate offsets from it
+    const uint32_t* __restrict__ q = static_cast<const uint32_t*>(soa) +
+                                     (static_cast<uint64_t>(g / per) * (D * plane) + (g % per) * 64u + lane);
 #pragma unroll
-    for (int t = 0; t < D; ++t) rows[t] = __builtin_nontemporal_load(s32 + (base + t * plane));
+    for (int t = 0; t < D; ++t) rows[t] = __builtin_nontemporal_load(q + t * plane);
 }
 
-// Filter the columns of one chunk; passing columns are compacted per wave into
-// the workgroup's LDS queue, or the global overflow queue once it is full.
+// Filter the columns of one chunk (half a chunk for 16-bit rows) and append
+// the passing ones to the workgroup's LDS queue.  Only LDS is written here:
+// once the queue is full, positions are clamped to its last slot and the
+// overflow flag is raised (the queue is then discarded and the workgroup's
+// chunks are filtered again, see vote_phase).
 template <int D>
-__device__ __forceinline__ void filter_and_queue(const SolveParams& p, int os, const uint32_t (&w)[D],
-                                                 uint32_t j, uint32_t n, uint32_t lane, int* q_items,
-                                                 int* q_count) {
+__device__ __forceinline__ void filter_and_queue(const SolveParams& p, const uint32_t (&w)[D], uint32_t j,
+                                                 uint32_t n, uint32_t lane, int* q_items, int* q_count,
+                                                 int* q_ovf) {
     const bool pass = bucket_filter<D>(w, p.a, p.rule) && j < n;
     const unsigned long long mask = __ballot(pass);
     if (mask) {
         int base = 0;
         if (lane == 0) base = atomicAdd(q_count, __popcll(mask));
         base = __shfl(base, 0);
-        if (pass) {
-            const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-            if (pos < kQueue) {
-                q_items[pos] = static_cast<int>(j);
-            } else {
-                const int gp = atomicAdd(&p.ovc[os], 1);
-                p.overflow[gp] = static_cast<int>(j);
-            }
-        }
+        const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (pass) q_items[pos < kQueue ? pos : kQueue - 1] = static_cast<int>(j);
+        if (lane == 0 && base + __popcll(mask) > kQueue) *q_ovf = 1;
     }
 }
 
-// Vote phase.  Waves stride over chunks, prefetching the next chunk's row
-// indices while the current chunk gathers its rows' bucket words and runs the
-// bucket filter.  Columns passing it are scored exactly once the chunks are
-// done, on the same residual.
-// l: the iteration (update counters); os: the overflow-count slot of this
-// pass; pos: the position shifted rules try in this pass.
+// Filter one chunk whose row indices are in `rows`.
+template <int D, bool COMPACT>
+__device__ __forceinline__ void filter_chunk(const SolveParams& p, const uint32_t* words, const uint32_t (&rows)[D],
+                                             uint32_t g, uint32_t n, uint32_t lane, int* q_items, int* q_count,
+                                             int* q_ovf) {
+    if constexpr (COMPACT) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint32_t w[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) w[t] = words[h ? (rows[t] >> 16) : (rows[t] & 0xFFFFu)];
+            filter_and_queue<D>(p, w, g * Chunk<true>::kCols + 2 * lane + h, n, lane, q_items, q_count, q_ovf);
+        }
+    } else {
+        uint32_t w[D];
+#pragma unroll
+        for (int t = 0; t < D; ++t) w[t] = words[rows[t]];
+        filter_and_queue<D>(p, w, g * Chunk<false>::kCols + lane, n, lane, q_items, q_count, q_ovf);
+    }
+}
+
+// Vote phase.  Each wave streams its chunks (g = wave, wave + stride, ...)
+// with two chunks' row indices in flight (two register buffers taking turns,
+// so no copy waits on a load), gathers the rows' bucket words and runs the
+// bucket filter; the loop issues no global store, so its waits cover loads
+// only.  Columns passing the filter are then scored exactly on the same
+// residual.  If the workgroup's queue overflowed, the queue is dropped and
+// the workgroup filters its chunks again, scoring each passing column at
+// once (slow, but only for inputs where the filter passes thousands of
+// columns per workgroup).  Chunks are assigned statically: handing them out
+// through atomic counters costs more than the imbalance it removes (a wave
+// cannot wait for a chunk's loads without also waiting for an older claim).
+// l: the iteration (update counters); pos: the position shifted rules try in
+// this pass.
 template <int D, bool COMPACT>
 __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32_t* lds_w,
-                           int* q_items, int* q_count, int os, int pos) {
+                           int* q_items, int* q_count, int* q_ovf, int pos) {
     const uint32_t lane = threadIdx.x & 63;
-    constexpr uint32_t kCols = Chunk<COMPACT>::kCols;
     const uint32_t nchunks = static_cast<uint32_t>(p.ntiles) * Chunk<COMPACT>::kPerTile;
     const uint32_t n = static_cast<uint32_t>(p.n);
     const uint32_t* __restrict__ words = COMPACT ? lds_w : p.rword;
     const uint32_t stride = gridDim.x * kWaves;
-    uint32_t g = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    uint32_t cur[D];
-#pragma unroll
-    for (int t = 0; t < D; ++t) cur[t] = 0;
-    if (g < nchunks) load_chunk<D, COMPACT>(p.soa, g, lane, cur);
-    for (; g < nchunks; g += stride) {
-        uint32_t nxt[D];
-#pragma unroll
-        for (int t = 0; t < D; ++t) nxt[t] = 0;
-        if (g + stride < nchunks) load_chunk<D, COMPACT>(p.soa, g + stride, lane, nxt);
-        if constexpr (COMPACT) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                uint32_t w[D];
-#pragma unroll
-                for (int t = 0; t < D; ++t) w[t] = words[h ? (cur[t] >> 16) : (cur[t] & 0xFFFFu)];
-                filter_and_queue<D>(p, os, w, g * kCols + 2 * lane + h, n, lane, q_items, q_count);
-            }
-        } else {
-            uint32_t w[D];
-#pragma unroll
-            for (int t = 0; t < D; ++t) w[t] = words[cur[t]];
-            filter_and_queue<D>(p, os, w, g * kCols + lane, n, lane, q_items, q_count);
-        }
-#pragma unroll
-        for (int t = 0; t < D; ++t) cur[t] = nxt[t];
+    const uint32_t first = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    // prefetches past the last chunk read the last chunk again (an L2 hit;
+    // unconditional loads keep the waits exact)
+    const uint32_t last = nchunks - 1;
+    uint32_t g = first;
+    uint32_t a[D], b[D];
+    load_chunk<D, COMPACT>(p.soa, min(g, last), lane, a);
+    load_chunk<D, COMPACT>(p.soa, min(g + stride, last), lane, b);
+    while (g < nchunks) {
+        filter_chunk<D, COMPACT>(p, words, a, g, n, lane, q_items, q_count, q_ovf);
+        load_chunk<D, COMPACT>(p.soa, min(g + 2 * stride, last), lane, a);
+        g += stride;
+        if (g >= nchunks) break;
+        filter_chunk<D, COMPACT>(p, words, b, g, n, lane, q_items, q_count, q_ovf);
+        load_chunk<D, COMPACT>(p.soa, min(g + 2 * stride, last), lane, b);
+        g += stride;
     }
     __syncthreads();
     if (p.timeline && blockIdx.x == 0 && threadIdx.x == 0)
         p.timeline[3 * p.max_iter + 9 + 3 * l] = static_cast<int64_t>(wall_clock64());
-    const int cnt = min(*q_count, kQueue);
-    for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D, COMPACT>(p, l, q_items[q], tau, pos);
+    if (*q_ovf == 0) {
+        const int cnt = *q_count;
+        for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D, COMPACT>(p, l, q_items[q], tau, pos);
+    } else {
+        // overflow: every chunk of this wave again, passing columns scored directly
+        constexpr uint32_t kCols = Chunk<COMPACT>::kCols;
+        for (uint32_t c = first; c < nchunks; c += stride) {
+            uint32_t rows[D];
+            load_chunk<D, COMPACT>(p.soa, c, lane, rows);
+#pragma unroll
+            for (int h = 0; h < (COMPACT ? 2 : 1); ++h) {
+                uint32_t w[D];
+#pragma unroll
+                for (int t = 0; t < D; ++t)
+                    w[t] = words[COMPACT ? (h ? (rows[t] >> 16) : (rows[t] & 0xFFFFu)) : rows[t]];
+                const uint32_t j = c * kCols + (COMPACT ? 2 * lane + h : lane);
+                if (bucket_filter<D>(w, p.a, p.rule) && j < n) score_exact<D, COMPACT>(p, l, j, tau, pos);
+            }
+        }
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         *q_count = 0;
+        *q_ovf = 0;
         if (p.timeline && blockIdx.x == 0)
             p.timeline[3 * p.max_iter + 10 + 3 * l] = static_cast<int64_t>(wall_clock64());
     }
@@ -303,8 +337,8 @@ template <int D, bool COMPACT>
 __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(SolveParams p, uint64_t limit) {
     extern __shared__ uint32_t lds_w[];
     __shared__ int q_items[kQueue];
-    __shared__ int q_count;
-    if (threadIdx.x == 0) q_count = 0;
+    __shared__ int q_count, q_ovf;
+    if (threadIdx.x == 0) q_count = q_ovf = 0;
     const int tid = threadIdx.x;
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
     const int64_t gsize = static_cast<int64_t>(gridDim.x) * kBlock;
@@ -398,9 +432,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
 
     // Vote passes are counted apart from iterations: a shifted rule's pass
     // that selects nothing is followed by another (the next position) and
-    // the run stalls after D such passes in a row.  Overflow counts use a
-    // ring of three slots by pass: slot pass+1 was last read before the
-    // barrier that ended pass - 1, so thread 0 clears it during this pass.
+    // the run stalls after D such passes in a row.
     int l = 0, pass = 0, empty = 0;
     const bool shifted = rule_is_shifted(p.rule);
     int outcome;
@@ -408,8 +440,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     for (;;) {
         if (nnz == 0) { outcome = L0_CONVERGED; break; }
         if (l == p.max_iter) { outcome = L0_MAX_ITER; break; }
-        const int os = pass % 3, pos = pass % D;
-        if (gtid == 0) p.ovc[(pass + 1) % 3] = 0;
+        const int pos = pass % D;
 
         // vote on the same residual for every column
         if (COMPACT) {
@@ -434,20 +465,10 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             if (p.timeline && blockIdx.x == 0 && tid == 0)
                 p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
         }
-        vote_phase<D, COMPACT>(p, l, tau, lds_w, q_items, &q_count, os, pos);
+        vote_phase<D, COMPACT>(p, l, tau, lds_w, q_items, &q_count, &q_ovf, pos);
         if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
             return;
-        }
-        // columns that overflowed the workgroup queues are scored now, still
-        // on the residual every other column saw
-        const int novf = ld_relaxed(&p.ovc[os]);
-        if (novf > 0) {
-            for (int64_t q = gtid; q < novf; q += gsize) score_exact<D, COMPACT>(p, l, p.overflow[q], tau, pos);
-            if (!grid_sync(c, site, limit, p.timeline)) {
-                if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
-                return;
-            }
         }
         ++pass;
         const int tc = ld_relaxed(&p.tcount[l]);
@@ -554,7 +575,7 @@ __global__ void __launch_bounds__(1024) repack_kernel(const int32_t* col_idx, Ma
 #pragma unroll
         for (int gi = 0; gi < G; ++gi) {
             const int64_t g = g0 + gi;
-            if (g >= ngroups) break;
+            if (g >= ngroups) continue;  // uniform across the wave
             const int64_t e0 = g * 64 * D + lane;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
@@ -749,12 +770,12 @@ hipError_t solve_d(const SolveParams& p, hipStream_t s) {
     int32_t* const ctrl_ints = reinterpret_cast<int32_t*>(p.ctrl);
     if (p.tcount >= ctrl_ints + sizeof(Ctrl) / sizeof(int32_t) && p.tcount - ctrl_ints <= 4096) {
         hipLaunchKernelGGL(zero_ints, dim3(8), dim3(256), 0, s, ctrl_ints,
-                           static_cast<int64_t>(p.tcount - ctrl_ints) + 4 * (p.max_iter + 2));
+                           static_cast<int64_t>(p.tcount - ctrl_ints) + 2 * (p.max_iter + 2));
     } else {
         hipLaunchKernelGGL(zero_ints, dim3(1), dim3(256), 0, s, ctrl_ints,
                            static_cast<int64_t>(sizeof(Ctrl) / sizeof(int32_t)));
         hipLaunchKernelGGL(zero_ints, dim3(8), dim3(256), 0, s, p.tcount,
-                           static_cast<int64_t>(4 * (p.max_iter + 2)));
+                           static_cast<int64_t>(2 * (p.max_iter + 2)));
     }
     SolveParams q = p;
     uint64_t limit = barrier_limit_ticks();
