@@ -206,16 +206,19 @@ def main():
     A.solve_async(y, alpha, max_iter=max_iter, tol=tol, x=xs, res=rs, timeline=tl)
     torch.cuda.synchronize()
     tlv = tl.cpu().tolist()
-    nb = 3 + 2 * iters + (1 if outcome == 1 else 0)
-    phases_us = [round((tlv[i + 1] - tlv[i]) / 100.0, 1) for i in range(nb - 1) if tlv[i + 1] > 0]
+    # entry 0: kernel start; 1..: grid barriers; 3*max_iter+7: every workgroup started
+    bars = [tlv[0]] + [v for v in tlv[1:3 * max_iter + 7] if v > 0]
+    phases_us = [round((bars[i + 1] - bars[i]) / 100.0, 1) for i in range(len(bars) - 1)]
+    startup_us = round((tlv[3 * max_iter + 7] - tlv[0]) / 100.0, 1) if tlv[3 * max_iter + 7] else None
     sub = []
     for l in range(passes_of(iters, outcome)):
         b = 3 * max_iter + 8 + 3 * l
-        prev = tlv[2 + 2 * l]  # the barrier that opened this vote
-        if tlv[b + 2] > 0 and prev > 0:
+        if tlv[b + 2] > 0:
+            prev = max(v for v in bars if v <= tlv[b])  # the barrier that opened this vote
             sub.append([round((tlv[b] - prev) / 100.0, 1), round((tlv[b + 1] - tlv[b]) / 100.0, 1),
                         round((tlv[b + 2] - tlv[b + 1]) / 100.0, 1)])
-    print(f"[bench] phase timeline (us, between grid barriers): {phases_us}", file=sys.stderr, flush=True)
+    print(f"[bench] phase timeline (us, between grid barriers): {phases_us}; all workgroups started "
+          f"after {startup_us} us", file=sys.stderr, flush=True)
     print(f"[bench] vote sub-phases (us: stage, stream+filter, exact scoring): {sub}", file=sys.stderr,
           flush=True)
     ts = tsize[:iters].cpu().tolist()
@@ -276,7 +279,7 @@ def main():
                    "per_vote_pass_us": round(solve_avg * 1e3 / max(passes, 1), 2),
                    "vote_bytes_per_pass": vote_bytes, "prepare_ms": round(prep_ms, 3),
                    "solves_per_s_prepared": round(1e3 / solve_avg, 3),
-                   "phase_us": phases_us},
+                   "phase_us": phases_us, "startup_us": startup_us},
     }
     print(json.dumps(out), flush=True)
 

@@ -119,7 +119,8 @@ typedef struct {
     int64_t* tsize;        /* device int64[max_iter]: |T| of each iteration, or NULL */
     int64_t* timeline;     /* device int64[6*max_iter + 16] or NULL: device wall-clock ticks
                               (hipDeviceAttributeWallClockRate) seen by workgroup 0: entry 0
-                              at kernel start, entry e after the e-th grid-wide barrier;
+                              at kernel start, entry 3*max_iter+7 once every workgroup has
+                              started, entry e after the e-th grid-wide barrier;
                               entries 3*max_iter+8+3*l+{0,1,2} when the vote of iteration l
                               has staged the residual, streamed all columns, and scored the
                               columns that passed the filter */

@@ -145,6 +145,23 @@ __device__ int block_sum(int v) {
     return s_total;
 }
 
+// Maximum of a double over the workgroup; the result is valid in every thread.
+__device__ double block_max(double v) {
+    __shared__ double s_part[kWaves];
+    __shared__ double s_total;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kWaves; ++w) t = fmax(t, s_part[w]);
+        s_total = t;
+    }
+    __syncthreads();
+    return s_total;
+}
+
 __device__ __forceinline__ int64_t soa_index(int64_t j, int t, int d) {
     return ((j / kTile) * d + t) * kTile + (j % kTile);
 }
@@ -326,11 +343,14 @@ __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32
 // the persistent solve kernel
 // ---------------------------------------------------------------------------
 
-// Waves per SIMD the compiler must allow: two resident workgroups (8 waves)
-// for small degrees, one for large ones.
+// Waves per SIMD the compiler must allow: one resident workgroup per CU (4
+// waves), which leaves 128 VGPRs per lane (no spills).  Two workgroups per CU
+// (8 waves, 64 VGPRs) were measured slower: the second workgroup on a CU
+// streamed its share about a third slower than the first, and every pass
+// waited for it.
 template <int D>
 struct Occ {
-    static constexpr int kWavesPerEU = D <= 9 ? 8 : 4;
+    static constexpr int kWavesPerEU = 4;
 };
 
 template <int D, bool COMPACT>
@@ -349,15 +369,80 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
         return;
     }
+    if (p.timeline && blockIdx.x == 0 && tid == 0)
+        p.timeline[3 * p.max_iter + 7] = static_cast<int64_t>(wall_clock64());
 
+    // Without a resume vector and with the bucket words in LDS (y then has
+    // at most 36864 entries), every workgroup derives max |y|, tau, ||y||_0
+    // and all bucket words of r = y from y itself: no grid barrier is needed
+    // between the start-up and the first vote, and the first pass stages
+    // nothing.
+    const bool local_init = COMPACT && p.x_init == nullptr;
+
+    // (The local start reads y before the init below floods the memory
+    // system with the stores that clear x_hat.)
+    double ymax = 0.0;
+    int nnz = 0;
+    if (local_init) {
+        // max |y| over every row, in every workgroup (a maximum is exact in
+        // any order, so all workgroups agree); non-finite y is reported by
+        // the shares above
+        constexpr int U = 8;
+        double lmax = 0.0;
+        for (int base = 0; base < p.m; base += U * kBlock) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = p.y[min(base + u * kBlock + tid, p.m - 1)];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (isfinite(v[u])) lmax = fmax(lmax, fabs(v[u]));
+        }
+        ymax = block_max(lmax);
+    }
+    const double tau0 = (p.tol_mode == L0_TOL_RELATIVE) ? p.tol * ymax : p.tol;
+    if (local_init) {
+        // ||y||_0 and the bucket words of r = y: all of them into LDS, this
+        // workgroup's share also to the global word array
+        const double iw = 1.0 / bucket_width(tau0, ymax);
+        constexpr int U = 8;
+        int cnt = 0;
+        for (int base = 0; base < p.m; base += U * kBlock) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = p.y[min(base + u * kBlock + tid, p.m - 1)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = base + u * kBlock + tid;
+                if (i < p.m) {
+                    lds_w[i] = row_word(v[u], tau0, iw);
+                    cnt += fabs(v[u]) > tau0;
+                }
+            }
+        }
+        nnz = block_sum(cnt);
+        for (int64_t i = gtid; i < p.m; i += gsize) p.rword[i] = lds_w[i];
+        if (gtid == 0) __hip_atomic_store(&c->nnz, nnz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     // --- init: x_hat, support bitmap, per-row state, max |y|, finiteness of
     //     y, usable column weights
     {
         int bad_w = 0;
-        for (int64_t j = gtid; j < p.n; j += gsize) {
-            p.x[j] = p.x_init ? p.x_init[j] : 0.0;
-            if (p.w && !weight_ok(p.w[j])) bad_w = 1;
+        if (p.x_init) {
+            for (int64_t j = gtid; j < p.n; j += gsize) p.x[j] = p.x_init[j];
+        } else if ((reinterpret_cast<uintptr_t>(p.x) & 15) == 0) {
+            // streaming 16-byte stores: x_hat is not read again before the
+            // scores of the first vote touch a few of its entries
+            typedef double dbl2 __attribute__((ext_vector_type(2)));
+            dbl2* x2 = reinterpret_cast<dbl2*>(p.x);
+            const dbl2 z = {0.0, 0.0};
+            for (int64_t j = gtid; j < (p.n >> 1); j += gsize) __builtin_nontemporal_store(z, &x2[j]);
+            if (gtid == 0 && (p.n & 1)) p.x[p.n - 1] = 0.0;
+        } else {
+            for (int64_t j = gtid; j < p.n; j += gsize) p.x[j] = 0.0;
         }
+        if (p.w)
+            for (int64_t j = gtid; j < p.n; j += gsize)
+                if (!weight_ok(p.w[j])) bad_w = 1;
         if (wave_count(bad_w != 0) && (tid & 63) == 0) atomicOr(&c->err, kErrBadWeight);
         const int64_t nwords = (p.n + 31) >> 5;
         for (int64_t w = gtid; w < nwords; w += gsize) p.member[w] = 0u;
@@ -370,12 +455,15 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             p.slot_cnt[i] = 0;
             p.slot_sorted[i] = 0;
             p.aff_flag[i] = 0;
+            if (local_init) p.r[i] = yi;
         }
+        if (!local_init) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
-        if ((tid & 63) == 0 && lmax > 0.0)
-            atomicMax(reinterpret_cast<unsigned long long*>(&c->maxabs_bits),
-                      static_cast<unsigned long long>(__double_as_longlong(lmax)));
+            for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
+            if ((tid & 63) == 0 && lmax > 0.0)
+                atomicMax(reinterpret_cast<unsigned long long*>(&c->maxabs_bits),
+                          static_cast<unsigned long long>(__double_as_longlong(lmax)));
+        }
         if (wave_count(bad != 0) && (tid & 63) == 0) atomicOr(&c->err, kErrNonfiniteY);
         if (gtid == 0 && *p.bad_index) atomicOr(&c->err, kErrBadIndex);
     }
@@ -388,8 +476,9 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         if (gtid == 0) write_result(p, 0, error_outcome(err), 0, 0, 0);
         return;
     }
-    const double ymax = __longlong_as_double(static_cast<long long>(
-        __hip_atomic_load(&c->maxabs_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+    if (!local_init)
+        ymax = __longlong_as_double(static_cast<long long>(
+            __hip_atomic_load(&c->maxabs_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
     const double tau = (p.tol_mode == L0_TOL_RELATIVE) ? p.tol * ymax : p.tol;
     const double inv_w = 1.0 / bucket_width(tau, ymax);
 
@@ -411,8 +500,8 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         }
     }
 
-    // --- r = y - A x_hat and ||r||_0
-    {
+    // --- r = y - A x_hat and ||r||_0 (done above in the local start)
+    if (!local_init) {
         int wnz = 0;
         for (int64_t i = gtid; i < p.m; i += gsize) {
             const double ri = p.x_init ? row_residual(p, static_cast<int>(i)) : p.y[i];
@@ -422,12 +511,12 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         }
         const int b = block_sum((tid & 63) == 0 ? wnz : 0);
         if (tid == 0 && b) atomicAdd(&c->nnz, b);
+        if (!grid_sync(c, site, limit, p.timeline)) {
+            if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
+            return;
+        }
+        nnz = ld_relaxed(&c->nnz);
     }
-    if (!grid_sync(c, site, limit, p.timeline)) {
-        if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
-        return;
-    }
-    int nnz = ld_relaxed(&c->nnz);
     if (gtid == 0 && p.trace) p.trace[0] = nnz;
 
     // Vote passes are counted apart from iterations: a shifted rule's pass
@@ -442,8 +531,9 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         if (l == p.max_iter) { outcome = L0_MAX_ITER; break; }
         const int pos = pass % D;
 
-        // vote on the same residual for every column
-        if (COMPACT) {
+        // vote on the same residual for every column (the local start left
+        // the first pass's words in LDS)
+        if (COMPACT && !(local_init && pass == 0)) {
             // 16-byte loads (the word array is 256-byte aligned), four in
             // flight per thread before the LDS stores: 64 KiB of words per
             // round; the last m % 4 words one by one
@@ -462,9 +552,9 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             for (; i < m4; i += kBlock) dst4[i] = src4[i];
             for (int t = (m4 << 2) + tid; t < p.m; t += kBlock) lds_w[t] = p.rword[t];
             __syncthreads();
-            if (p.timeline && blockIdx.x == 0 && tid == 0)
-                p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
         }
+        if (p.timeline && blockIdx.x == 0 && tid == 0)
+            p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
         vote_phase<D, COMPACT>(p, l, tau, lds_w, q_items, &q_count, &q_ovf, pos);
         if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
