@@ -235,7 +235,8 @@ typedef struct {
     int32_t rule;          /* l0_rule for every instance */
     int32_t tol_mode;      /* l0_tol_mode for every instance */
     int32_t block_threads; /* 256 or 512 threads per workgroup (0: 256) */
-    int32_t words_cap;     /* bucket words in LDS when m <= words_cap (0: 8192; else 64..32768) */
+    int32_t words_cap;     /* bucket words kept in LDS: 32-bit when m <= words_cap, folded to
+                              16 bits when m <= 2*words_cap (0: 8192; else 64..32768) */
     int64_t* timing;       /* optional device int64[8*count]; record i (in ticks of the
                               device's constant 100 MHz clock): [0] start, [1] end,
                               [2] setup, [3] vote, [4] scoring and updates, [5] residual

@@ -441,14 +441,14 @@ bool plan_batch(const l0_problem* probs, int32_t count, int block_threads, int w
         }
         const int64_t resident = static_cast<int64_t>(per_cu) * (cus > 0 ? cus : 1);
         // Estimated cost of an instance: its column indices, three times over
-        // when its bucket words do not fit in LDS (the vote then gathers them
-        // from global memory, about three times slower).  The group's
+        // when its bucket words do not fit in LDS even folded to 16 bits (the
+        // vote then gathers them from global memory, about three times slower).  The group's
         // instances are claimed most costly first, and an instance gets one
         // team member per kTeamUnit of cost (at most kMaxTeam, never more
         // than the resident workgroups: members wait for each other).
         auto cost = [&](int32_t i) {
             const int64_t nd = probs[i].n * probs[i].d;
-            return probs[i].m <= g.words_cap ? nd : 3 * nd;
+            return probs[i].m <= 2 * static_cast<int64_t>(g.words_cap) ? nd : 3 * nd;
         };
         std::stable_sort(pl.order.begin() + g.inst_start, pl.order.begin() + g.inst_start + g.inst_count,
                          [&](int32_t a, int32_t b) { return cost(a) > cost(b); });

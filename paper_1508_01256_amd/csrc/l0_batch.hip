@@ -90,6 +90,7 @@ __device__ BlockState carve(char* base, const l0_problem& P) {
 
 struct Lds {
     lptr<uint32_t> words;  // words_cap entries (also the degree histogram)
+    lptr<uint16_t> hwords; // the same memory as 2 * words_cap folded 16-bit words
     lptr<int> stage;       // (blockDim/64) * 64 * D entries
     lptr<int> queue;       // kBatchQueue + (blockDim/64) * 64 entries
     lptr<int> red;         // 16 ints / 8 doubles of reduction scratch
@@ -222,10 +223,11 @@ __device__ __forceinline__ void load_group(gptr<const int32_t> col_idx, int64_t 
 // The ordinary pass has no branch and no global write in its loop body:
 // either would make the compiler drain all outstanding loads at the loop
 // head, serialising the index prefetch.  Lanes with nothing to queue store
-// to their discard slot instead.  WL: bucket words in LDS, else in global
+// to their discard slot instead.  WM: bucket words in LDS as 32-bit words
+// (1) or folded 16-bit words (2, twice as many rows), else (0) in global
 // memory.  Slots past the last group run on clamped indices and queue
 // nothing.
-template <int D, bool WL, bool SPILL>
+template <int D, int WM, bool SPILL>
 __device__ void vote_pass(gptr<const int32_t> col_idx, int64_t n, const BlockState& s, const Lds& L, int a, int rule,
                           int64_t first, int64_t stride, gptr<int> spill) {
     // groups in flight per wave: about 32 registers of indices
@@ -256,7 +258,7 @@ __device__ void vote_pass(gptr<const int32_t> col_idx, int64_t n, const BlockSta
 #pragma unroll
             for (int t = 0; t < D; ++t) {
                 const int row = stage[lane * D + t];
-                w[t] = WL ? L.words[row] : s.rword[row];
+                w[t] = WM == 1 ? L.words[row] : (WM == 2 ? unfold_word(L.hwords[row]) : s.rword[row]);
             }
             // refill this slot after the gathers are issued (the scheduler may
             // not hoist it): the gathers never wait for it, and it is in
@@ -303,12 +305,12 @@ __device__ void score_column(gptr<const int32_t> col_idx, const BlockState& s, i
 // The vote of one iteration for this member, with the exact scoring of the
 // columns it queued in LDS.  Returns true when its queue overflowed: its
 // columns then went to the team's shared list, scored after a team barrier.
-template <int D, bool WL>
+template <int D, int WM>
 __device__ bool vote_and_score(gptr<const int32_t> col_idx, int64_t n, const BlockState& s, const Lds& L, int a,
                                int rule, const Team& tm, gptr<IterCounters> ring, double tau, int pos) {
     const int nw = blockDim.x >> 6, qcap = kBatchQueue / nw;
     const int64_t first = static_cast<int64_t>(tm.rank) * nw, stride = static_cast<int64_t>(tm.size) * nw;
-    vote_pass<D, WL, false>(col_idx, n, s, L, a, rule, first, stride, nullptr);
+    vote_pass<D, WM, false>(col_idx, n, s, L, a, rule, first, stride, nullptr);
     __syncthreads();
     int total = 0;
     bool over = false;
@@ -317,7 +319,7 @@ __device__ bool vote_and_score(gptr<const int32_t> col_idx, int64_t n, const Blo
         over |= L.wq[w] > qcap;
     }
     if (over) {
-        vote_pass<D, WL, true>(col_idx, n, s, L, a, rule, first, stride, &ring->spill);
+        vote_pass<D, WM, true>(col_idx, n, s, L, a, rule, first, stride, &ring->spill);
         return true;
     }
     for (int q = threadIdx.x; q < total; q += blockDim.x) {
@@ -330,14 +332,15 @@ __device__ bool vote_and_score(gptr<const int32_t> col_idx, int64_t n, const Blo
 
 // Store the new residual of row i (and its bucket word); returns the change
 // of the row's nonzero indicator.
-__device__ __forceinline__ int finish_row(const BlockState& s, const Lds& L, bool wl, int i, double rn, double tau,
+__device__ __forceinline__ int finish_row(const BlockState& s, const Lds& L, int wm, int i, double rn, double tau,
                                           double inv_w) {
     const bool was = fabs(s.r[i]) > tau;
     const bool now = fabs(rn) > tau;
     s.r[i] = rn;
     const uint32_t w = row_word(rn, tau, inv_w);
     s.rword[i] = w;
-    if (wl) L.words[i] = w;
+    if (wm == 1) L.words[i] = w;
+    else if (wm == 2) L.hwords[i] = fold_word(w);
     s.aff_flag[i] = 0;
     return static_cast<int>(now) - static_cast<int>(was);
 }
@@ -459,7 +462,9 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
     const int64_t n = P.n;
     const int m = P.m;
     const int64_t nd = n * D;
-    const bool wl = m <= bp.words_cap;
+    // bucket words in LDS: 32-bit when m fits the word capacity, folded to
+    // 16 bits when it fits twice over, else read from global memory
+    const int wm = m <= bp.words_cap ? 1 : (m <= 2 * bp.words_cap ? 2 : 0);
     const int64_t gt = static_cast<int64_t>(rank) * nthr + tid, gstep = static_cast<int64_t>(tsize) * nthr;
 
     // --- init, split over the team: x_hat = 0, support bitmap, per-row
@@ -565,8 +570,10 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
     const int a = static_cast<int>(ceil(P.alpha));
     // bucket words: every member keeps all of them in LDS (when m fits);
     // the global copy and ||y||_0 are split over the team
-    if (wl)
+    if (wm == 1)
         for (int i = tid; i < m; i += nthr) L.words[i] = row_word(s.y[i], tau, inv_w);
+    else if (wm == 2)
+        for (int i = tid; i < m; i += nthr) L.hwords[i] = fold_word(row_word(s.y[i], tau, inv_w));
     int nzc = 0;
     for (int64_t i = gt; i < m; i += gstep) {
         const double yi = s.y[i];
@@ -599,8 +606,9 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         __syncthreads();
 
         // vote and exact scoring of this member's columns (Jacobi updates)
-        const bool spilled = wl ? vote_and_score<D, true>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos)
-                                : vote_and_score<D, false>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos);
+        const bool spilled = wm == 1   ? vote_and_score<D, 1>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos)
+                             : wm == 2 ? vote_and_score<D, 2>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos)
+                                       : vote_and_score<D, 0>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos);
         (void)spilled;
         if (lead && tid == 0) {
             const gptr<IterCounters> next = &tm.ctl->ring[(pass + 1) % 3];
@@ -650,11 +658,11 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
             const int i = s.aff_list[q];
             const int cnt = s.slot_cnt[i];
             if (cnt <= kShortList) {
-                delta += finish_row(s, L, wl, i, row_residual_any(s, i, cnt), tau, inv_w);
+                delta += finish_row(s, L, wm, i, row_residual_any(s, i, cnt), tau, inv_w);
             } else {
                 const int k = fetch_add(&L.ctr[0], 1);
                 if (k < long_cap) long_rows[k] = i;
-                else delta += finish_row(s, L, wl, i, row_residual(s, i), tau, inv_w);
+                else delta += finish_row(s, L, wm, i, row_residual(s, i), tau, inv_w);
             }
         }
         __syncthreads();
@@ -662,7 +670,7 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         for (int li = 0; li < nl; ++li) {
             const int i = long_rows[li];
             const double rn = long_row_residual(s, L, i);
-            if (tid == 0) delta += finish_row(s, L, wl, i, rn, tau, inv_w);
+            if (tid == 0) delta += finish_row(s, L, wm, i, rn, tau, inv_w);
         }
         delta = wg_sum(delta, L.red);
         if (tid == 0) fetch_add(&ring->delta, delta);
@@ -671,10 +679,11 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         updates += tc;
         ++l;
         // the other members' rows: refresh their words in this LDS copy
-        if (wl && tsize > 1) {
+        if (wm && tsize > 1) {
             for (int q = tid; q < na; q += nthr) {
                 const int i = s.aff_list[q];
-                L.words[i] = s.rword[i];
+                if (wm == 1) L.words[i] = s.rword[i];
+                else L.hwords[i] = fold_word(s.rword[i]);
             }
         }
         __syncthreads();
@@ -720,6 +729,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchParams bp) {
     __shared__ int s_item;
     Lds L;
     L.words = (lptr<uint32_t>)lds;
+    L.hwords = (lptr<uint16_t>)lds;
     L.stage = (lptr<int>)(lds + bp.words_cap);
     L.queue = L.stage + (BS / 64) * 64 * bp.stage_d;
     L.red = (lptr<int>)red;

@@ -133,6 +133,21 @@ L0_HD double bucket_width(double tau, double ymax) {
     return std::ldexp(1.0, e);
 }
 
+// 16-bit words for LDS copies of up to twice as many rows: bucket bit k of
+// a 32-bit word goes to bit k mod 15, the zero flag to bit 15.  Folding maps
+// a word holding t's bucket bit to one holding t's folded bit, so counts per
+// folded bit are never below the counts per original bit: the filter on
+// unfolded words stays a necessary condition (it only passes more columns).
+L0_HD uint16_t fold_word(uint32_t w) {
+    const uint32_t b = (w & 0x7FFFu) | ((w >> 15) & 0x7FFFu) | ((w >> 30) & 1u);
+    return static_cast<uint16_t>(b | ((w >> 16) & 0x8000u));
+}
+
+// A folded word back in the 32-bit layout (zero flag in bit 31).
+L0_HD uint32_t unfold_word(uint16_t h) {
+    return (static_cast<uint32_t>(h) & 0x7FFFu) | ((static_cast<uint32_t>(h) & 0x8000u) << 16);
+}
+
 // Bit-sliced population count of D words: c[k] holds bit k of the per-bit-
 // position count.  Full adders (xor / majority) for the common degrees, a
 // ripple-carry accumulation otherwise.

@@ -3,7 +3,8 @@
 //  2. bucket_filter<D> equals its definition on random words;
 //  3. exact_score<D> equals the l0-decrease eq. (selection_l0) formed entry
 //     by entry, best score first and smallest value on ties;
-//  4. the filter never rejects a column exact_score selects, on adversarial
+//  4. the filter (on 32-bit words, and on words folded to 16 bits) never
+//     rejects a column exact_score selects, on adversarial
 //     columns (clusters within tau, zeros, tiny values, values straddling
 //     bucket edges) for several tau, both rules and every threshold.
 // Exit status 0 and "OK" on success.
@@ -65,7 +66,7 @@ template <int D>
 static int check_exactness(int trials) {
     const double ymax = 3.0;
     const double taus[] = {0.0, 1e-10 * ymax, 1e-6 * ymax, 1e-3 * ymax, 0x1p-40, 0.37};
-    long selected = 0, passed = 0;
+    long selected = 0, passed = 0, folded_passed = 0;
     for (double tau : taus) {
         const double width = bucket_width(tau, ymax);
         const double inv_w = 1.0 / width;
@@ -125,6 +126,20 @@ static int check_exactness(int trials) {
                         for (int t = 0; t < D; ++t) std::printf("  v=%.17g w=%08x\n", v[t], w[t]);
                         return 1;
                     }
+                    // folded 16-bit words: the filter passes at least what the
+                    // 32-bit filter passes (so every selected column)
+                    uint32_t wf[D];
+                    for (int t = 0; t < D; ++t) {
+                        wf[t] = unfold_word(fold_word(w[t]));
+                        if ((wf[t] >> 31) != (w[t] >> 31)) { std::printf("fold lost the zero flag\n"); return 1; }
+                    }
+                    const bool fpass = bucket_filter<D>(wf, a, rule);
+                    folded_passed += fpass;
+                    if (pass && !fpass) {
+                        std::printf("FOLDED FILTER REJECTED A PASSING COLUMN D=%d tau=%g a=%d rule=%d\n", D, tau, a,
+                                    rule);
+                        return 1;
+                    }
                     // shifted rule (Algorithm 3): candidate v[t] only, by its
                     // definition; the filter (with the shifted rule's zero
                     // term) must pass every column it selects
@@ -147,7 +162,7 @@ static int check_exactness(int trials) {
                             std::printf("exact_score_shifted D=%d t=%d mismatch\n", D, t);
                             return 1;
                         }
-                        if (ssel && !bucket_filter<D>(w, a, srule)) {
+                        if (ssel && (!bucket_filter<D>(w, a, srule) || !bucket_filter<D>(wf, a, srule))) {
                             std::printf("FILTER REJECTED A SHIFTED SELECTION D=%d tau=%g a=%d rule=%d\n", D, tau, a,
                                         srule);
                             return 1;
@@ -156,7 +171,7 @@ static int check_exactness(int trials) {
                 }
         }
     }
-    std::printf("D=%d selected=%ld passed=%ld\n", D, selected, passed);
+    std::printf("D=%d selected=%ld passed=%ld passed with folded words=%ld\n", D, selected, passed, folded_passed);
     return 0;
 }
 
