@@ -214,7 +214,11 @@ l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter,
  * one workgroup and a large one to a team of up to 256 (never more than are
  * resident) that split its columns and rows.  Workspace covers each instance's own scratch.  Each instance's result is
  * bitwise the one l0_decode_ex gives it alone.  Instances must not share
- * x_out buffers.
+ * x_out buffers.  A call plans its teams for the whole device: calls that
+ * overlap on one device (other streams) are not supported, since their
+ * teams could wait for members that cannot be scheduled until a 20 s bound
+ * aborts them (L0_DEV_ABORTED); the server (l0_server_*) runs its
+ * concurrent batches within a share of the device each.
  */
 typedef struct {
     const int32_t* col_idx; /* device int32[n*d], as l0_decode */

@@ -355,7 +355,8 @@ struct BatchPlan {
 };
 
 constexpr size_t kLdsLimit = 160 * 1024 - 1024;  // dynamic LDS bound (static use is < 1 KiB)
-constexpr int64_t kTeamUnit = int64_t(1) << 19;  // estimated cost per team member
+constexpr int64_t kTeamUnit = int64_t(1) << 19;     // estimated cost per team member (large batches)
+constexpr int64_t kMinTeamUnit = int64_t(1) << 15;  // least cost per team member (small batches)
 
 bool batch_opts_ok(const l0_batch_opts* o) {
     if (!o) return true;
@@ -414,7 +415,12 @@ bool problems_ok(const l0_problem* probs, int32_t count, BatchPlan& pl, bool buf
 
 // Resident workgroups, LDS, team sizes and work items of every group for
 // one schedule (block size, bucket-word capacity); false if infeasible.
-bool plan_batch(const l0_problem* probs, int32_t count, int block_threads, int words_cap, BatchPlan& pl) {
+// share: the number of batches that may run on the device at once (each is
+// planned within an equal share of the resident workgroups, so that all of
+// them can be resident together and no team waits for members that cannot be
+// scheduled).
+bool plan_batch(const l0_problem* probs, int32_t count, int block_threads, int words_cap, BatchPlan& pl,
+                int share = 1) {
     pl.block_threads = block_threads;
     pl.words_cap = words_cap;
     const int cus = l0::device_cus();
@@ -439,13 +445,14 @@ bool plan_batch(const l0_problem* probs, int32_t count, int block_threads, int w
             (void)hipGetLastError();
             return false;
         }
-        const int64_t resident = static_cast<int64_t>(per_cu) * (cus > 0 ? cus : 1);
+        const int64_t resident =
+            std::max<int64_t>(1, static_cast<int64_t>(per_cu) * (cus > 0 ? cus : 1) / std::max(1, share));
         // Estimated cost of an instance: its column indices, three times over
         // when its bucket words do not fit in LDS even folded to 16 bits (the
         // vote then gathers them from global memory, about three times slower).  The group's
         // instances are claimed most costly first, and an instance gets one
-        // team member per kTeamUnit of cost (at most kMaxTeam, never more
-        // than the resident workgroups: members wait for each other).
+        // team member per unit of cost (at most kMaxTeam, never more than the
+        // resident workgroups: members wait for each other).
         auto cost = [&](int32_t i) {
             const int64_t nd = probs[i].n * probs[i].d;
             return probs[i].m <= 2 * static_cast<int64_t>(g.words_cap) ? nd : 3 * nd;
@@ -453,10 +460,16 @@ bool plan_batch(const l0_problem* probs, int32_t count, int block_threads, int w
         std::stable_sort(pl.order.begin() + g.inst_start, pl.order.begin() + g.inst_start + g.inst_count,
                          [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
         const int64_t tmax = std::min<int64_t>(l0::kMaxTeam, resident);
+        // A batch too small to fill the resident workgroups at kTeamUnit per
+        // member (a few requests of a server, one large instance) gets a
+        // smaller unit, so that its teams spread over the whole device.
+        int64_t total = 0;
+        for (int32_t q = g.inst_start; q < g.inst_start + g.inst_count; ++q) total += cost(pl.order[q]);
+        const int64_t unit = std::max<int64_t>(kMinTeamUnit, std::min<int64_t>(kTeamUnit, total / resident));
         g.item_start = static_cast<int32_t>(pl.items.size());
         for (int32_t q = g.inst_start; q < g.inst_start + g.inst_count; ++q) {
             const int32_t i = pl.order[q];
-            const int t = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(tmax, (cost(i) + kTeamUnit - 1) / kTeamUnit)));
+            const int t = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(tmax, (cost(i) + unit - 1) / unit)));
             pl.team[i] = t;
             for (int r = 0; r < t; ++r) pl.items.push_back(i | (r << l0::kItemInstBits));
         }
@@ -533,6 +546,27 @@ l0_status launch_batch(const l0_problem* probs, int32_t count, const l0_batch_op
 
 }  // namespace
 
+namespace l0 {
+
+l0_status decode_batched_share(const l0_problem* probs, int32_t count, const l0_batch_opts* opts, l0_result* results,
+                               void* workspace, size_t ws_bytes, hipStream_t stream, int share) {
+    if (!batch_opts_ok(opts) || share < 1) return L0_ERR_ARG;
+    BatchPlan pl;
+    if (!problems_ok(probs, count, pl, true)) return L0_ERR_ARG;
+    if (!buffer_ok(results, sizeof(l0_result) * static_cast<size_t>(count))) return L0_ERR_ARG;
+    if (opts && opts->timing && !buffer_ok(opts->timing, 8 * sizeof(int64_t) * static_cast<size_t>(count)))
+        return L0_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return L0_ERR_ARG;
+    int bt, wc;
+    resolve(opts, bt, wc);
+    if (!plan_batch(probs, count, bt, wc, pl, share)) return L0_ERR_ARG;
+    if (ws_bytes < pl.total) return L0_ERR_WORKSPACE;
+    if (!buffer_ok(workspace, pl.total)) return L0_ERR_ARG;
+    return launch_batch(probs, count, opts, pl, results, static_cast<char*>(workspace), stream);
+}
+
+}  // namespace l0
+
 extern "C" {
 
 size_t l0_batch_workspace_bytes(const l0_problem* probs, int32_t count, const l0_batch_opts* opts) {
@@ -552,19 +586,7 @@ size_t l0_batch_workspace_bytes(const l0_problem* probs, int32_t count, const l0
 
 l0_status l0_decode_batched(const l0_problem* probs, int32_t count, const l0_batch_opts* opts,
                             l0_result* results, void* workspace, size_t ws_bytes, hipStream_t stream) {
-    if (!batch_opts_ok(opts)) return L0_ERR_ARG;
-    BatchPlan pl;
-    if (!problems_ok(probs, count, pl, true)) return L0_ERR_ARG;
-    if (!buffer_ok(results, sizeof(l0_result) * static_cast<size_t>(count))) return L0_ERR_ARG;
-    if (opts && opts->timing && !buffer_ok(opts->timing, 8 * sizeof(int64_t) * static_cast<size_t>(count)))
-        return L0_ERR_ARG;
-    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return L0_ERR_ARG;
-    int bt, wc;
-    resolve(opts, bt, wc);
-    if (!plan_batch(probs, count, bt, wc, pl)) return L0_ERR_ARG;
-    if (ws_bytes < pl.total) return L0_ERR_WORKSPACE;
-    if (!buffer_ok(workspace, pl.total)) return L0_ERR_ARG;
-    return launch_batch(probs, count, opts, pl, results, static_cast<char*>(workspace), stream);
+    return l0::decode_batched_share(probs, count, opts, results, workspace, ws_bytes, stream, 1);
 }
 
 l0_status l0_batch_autotune(const l0_problem* probs, int32_t count, l0_batch_opts* opts, l0_result* results,

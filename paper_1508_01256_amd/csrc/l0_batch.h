@@ -105,4 +105,12 @@ inline int batch_range_of(int d) {
 // nullptr.
 const void* batch_kernel_fn(int block_threads, int range);
 
+// l0_decode_batched planned within 1/share of the device's resident
+// workgroups (grid and teams), for callers that run up to `share` batches on
+// the device at once: they can then all be resident together, so no team
+// waits for members that cannot be scheduled.
+l0_status decode_batched_share(const l0_problem* probs, int32_t count, const l0_batch_opts* opts,
+                               l0_result* results, void* workspace, size_t ws_bytes, hipStream_t stream,
+                               int share);
+
 }  // namespace l0

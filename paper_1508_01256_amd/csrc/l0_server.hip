@@ -13,6 +13,16 @@
 // budget.  Each slot has a stream and an event of its own (default
 // priority), so a new batch can start while an earlier one drains its last,
 // largest instances.
+//
+// Batches that may run together are planned within an equal share of the
+// device's resident workgroups (one share per slot), so that all of them fit
+// on the device at once and no team waits for members that cannot be
+// scheduled.  A batch of at most kExclusiveMax requests launched while the
+// server is idle gets the whole device instead (lowest latency at low load);
+// nothing else is launched until it has finished.  A large request (at least
+// kSoloIndices column indices) is decoded alone by the single-instance
+// decoder (l0_decode_ex), which streams at the device's full rate; it waits,
+// in arrival order, until no batch is running, and runs alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,12 +33,17 @@
 #include <mutex>
 #include <vector>
 
+#include "l0_batch.h"
 #include "l0_internal.h"
 #include "l0decode.h"
 
 namespace {
 
 constexpr int kMaxSlots = 4;
+constexpr size_t kExclusiveMax = 2;
+constexpr int64_t kSoloIndices = int64_t(1) << 21;
+
+bool is_large(const l0_problem& p) { return p.n * p.d >= kSoloIndices; }
 
 struct Request {
     l0_problem p;
@@ -52,6 +67,8 @@ struct Slot {
     hipEvent_t done_event = nullptr;
     l0_result* host_res = nullptr;  // host memory the device writes, max_batch records
     l0_status status = L0_OK;
+    bool exclusive = false;    // planned for the whole device
+    bool solo = false;         // one request on the single-instance decoder
 };
 
 
@@ -119,6 +136,8 @@ void release_slot(Slot& sl) {
     sl.done.clear();
     sl.remaining = 0;
     sl.busy = false;
+    sl.exclusive = false;
+    sl.solo = false;
 }
 
 // Fail every request of the slot that has not completed.
@@ -134,7 +153,9 @@ void collect(l0_server_s* s, bool wait) {
     for (Slot& sl : s->slots) {
         if (!sl.busy) continue;
         const double t = s->now();
-        for (size_t q = 0; q < sl.reqs.size() && sl.remaining; ++q) {
+        // a batch writes each outcome last; the single-instance decoder does
+        // not, so its request completes with its event
+        for (size_t q = 0; q < sl.reqs.size() && sl.remaining && !sl.solo; ++q) {
             if (sl.done[q]) continue;
             const int32_t oc = __atomic_load_n(&sl.host_res[q].outcome, __ATOMIC_ACQUIRE);
             if (oc != kPending) complete_one(s, sl, q, L0_OK, t);
@@ -157,15 +178,64 @@ void collect(l0_server_s* s, bool wait) {
     }
 }
 
+// Decode the first waiting request alone with the single-instance decoder on
+// this (free) slot; the server is otherwise idle.
+void launch_solo(l0_server_s* s, Slot& sl) {
+    const Request r = s->waiting.front();
+    s->waiting.pop_front();
+    const l0_problem& P = r.p;
+    const size_t ws = l0_workspace_bytes(P.n, P.m, P.d, P.max_iter);
+    const size_t at = ws ? find_range(s, ws) : SIZE_MAX;
+    sl.reqs.assign(1, r);
+    sl.done.assign(1, 0);
+    sl.remaining = 1;
+    sl.off = at == SIZE_MAX ? 0 : at;
+    sl.size = at == SIZE_MAX ? 0 : ws;
+    sl.busy = true;
+    sl.exclusive = true;
+    sl.solo = true;
+    sl.launch_s = s->now();
+    std::memset(&sl.host_res[0], 0, sizeof(l0_result));
+    sl.host_res[0].outcome = kPending;
+    l0_opts o{};
+    o.rule = s->opts.batch.rule;
+    o.tol_mode = s->opts.batch.tol_mode;
+    o.weights = P.weights;
+    l0_status st = at == SIZE_MAX ? L0_ERR_WORKSPACE
+                                  : l0_decode_ex(P.col_idx, P.n, P.m, P.d, P.y, P.alpha, P.max_iter, P.tol,
+                                                 P.x_out, &o, sl.host_res, s->arena + at, ws, sl.stream);
+    if (st == L0_OK && hipEventRecord(sl.done_event, sl.stream) != hipSuccess) st = L0_ERR_HIP;
+    if (st != L0_OK) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(sl.stream);
+        fail_rest(s, sl, st);
+        release_slot(sl);
+    }
+}
+
 // Launch batches into free slots while requests wait.
 l0_status launch(l0_server_s* s) {
     const int32_t max_batch = s->opts.max_batch ? s->opts.max_batch : 1024;
+    const int nslots = static_cast<int>(s->slots.size());
     for (Slot& sl : s->slots) {
         if (s->waiting.empty()) break;
         if (sl.busy) continue;
-        // take waiting requests in order while their bound fits a free range
+        int busy = 0;
+        bool exclusive_running = false;
+        for (const Slot& o : s->slots) {
+            busy += o.busy;
+            exclusive_running |= o.busy && o.exclusive;
+        }
+        if (exclusive_running) break;  // wait for the whole-device batch
+        if (is_large(s->waiting.front().p)) {
+            if (busy) break;  // it runs alone
+            launch_solo(s, sl);
+            break;
+        }
+        // take waiting small requests in order while their bound fits a free range
         size_t bound = 0, take = 0;
-        while (take < s->waiting.size() && take < static_cast<size_t>(max_batch)) {
+        while (take < s->waiting.size() && take < static_cast<size_t>(max_batch) &&
+               !is_large(s->waiting[take].p)) {
             const size_t next = bound + s->waiting[take].bound;
             if (find_range(s, next) == SIZE_MAX) break;
             bound = next;
@@ -190,8 +260,11 @@ l0_status launch(l0_server_s* s) {
             sl.host_res[q].outcome = kPending;
         }
         std::atomic_thread_fence(std::memory_order_seq_cst);
-        l0_status st = l0_decode_batched(probs.data(), static_cast<int32_t>(take), &s->opts.batch, sl.host_res,
-                                         s->arena + at, ws, sl.stream);
+        // the whole device when idle and the batch is small, else one share
+        sl.exclusive = busy == 0 && take <= kExclusiveMax;
+        l0_status st = l0::decode_batched_share(probs.data(), static_cast<int32_t>(take), &s->opts.batch,
+                                                sl.host_res, s->arena + at, ws, sl.stream,
+                                                sl.exclusive ? 1 : nslots);
         if (st == L0_OK && hipEventRecord(sl.done_event, sl.stream) != hipSuccess) st = L0_ERR_HIP;
         if (st != L0_OK) {
             (void)hipGetLastError();
@@ -200,6 +273,8 @@ l0_status launch(l0_server_s* s) {
             (void)hipStreamSynchronize(sl.stream);
             fail_rest(s, sl, st);
             release_slot(sl);
+        } else if (sl.exclusive) {
+            break;  // nothing runs beside it
         }
     }
     return L0_OK;
@@ -260,8 +335,9 @@ l0_status l0_server_submit(l0_server s, const l0_problem* prob, int64_t id) {
     if (!s || !prob) return L0_ERR_ARG;
     // host checks of sizes and scalars (a one-instance batch that cannot be
     // planned is invalid), then the buffers
-    const size_t one = l0_batch_workspace_bytes(prob, 1, &s->opts.batch);
+    size_t one = l0_batch_workspace_bytes(prob, 1, &s->opts.batch);
     if (one == 0) return L0_ERR_ARG;
+    if (is_large(*prob)) one = std::max(one, l0_workspace_bytes(prob->n, prob->m, prob->d, prob->max_iter));
     if (!l0::device_buffer_ok(prob->col_idx, static_cast<size_t>(prob->n) * prob->d * sizeof(int32_t)) ||
         !l0::device_buffer_ok(prob->y, static_cast<size_t>(prob->m) * sizeof(double)) ||
         !l0::device_buffer_ok(prob->x_out, static_cast<size_t>(prob->n) * sizeof(double)) ||

@@ -131,3 +131,36 @@ def test_column_scaled_requests():
     bufs = upload(insts)
     done = run_server(insts, bufs, max_inflight=2)
     check_against_oracle(insts, bufs, done, "scaled")
+
+
+def test_concurrent_batches_share_the_device():
+    """Requests just below the size that goes to the single-instance decoder,
+    through four slots at once: batches in flight together are planned within
+    a share of the device each, so none of their teams waits for members
+    that cannot be scheduled (every result completes and equals the oracle's,
+    none is aborted)."""
+    rng = np.random.Generator(np.random.PCG64(27))
+    insts = []
+    for q in range(16):
+        n = int(rng.choice([1 << 17, 3 << 16, 1 << 18]))
+        m = int(0.01 * n) if q % 2 else int(0.1 * n)
+        insts.append(gen.make_instance(27000 + q, n, m, 7, gen.mk_k(m, 0.1)))
+    bufs = upload(insts)
+    say("concurrent batches", len(insts))
+    done = run_server(insts, bufs, budget=8 << 30, max_inflight=4, max_batch=3)
+    check_against_oracle(insts, bufs, done, "concurrent")
+    assert all(c["outcome"] != l0.L0_DEV_ABORTED for c in done.values())
+
+
+def test_large_and_small_requests_mixed():
+    """Large requests (decoded alone by the single-instance decoder) between
+    small batched ones, each result equal to the oracle's."""
+    insts = []
+    for q in range(10):
+        if q % 3 == 0:
+            insts.append(gen.make_instance(28000 + q, 1 << 19, 5243, 7, 500))   # 3.7 M indices
+        else:
+            insts.append(gen.make_instance(28000 + q, 3000 + 500 * q, 300 + 50 * q, 7, 20))
+    bufs = upload(insts)
+    done = run_server(insts, bufs, budget=4 << 30, max_inflight=2)
+    check_against_oracle(insts, bufs, done, "mixed-large")
