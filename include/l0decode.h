@@ -200,10 +200,31 @@ size_t l0_solve_workspace_bytes(l0_matrix A, int32_t max_iter);
 /*
  * Decode y against a prepared matrix.  Arguments as l0_decode_ex, with the
  * workspace sized by l0_solve_workspace_bytes.
+ *
+ * The solve (here and in l0_decode / l0_decode_ex) is one persistent kernel
+ * of up to one workgroup per compute unit, launched as an ordinary kernel.
+ * Its workgroups admit themselves at start: the ones that start become the
+ * members, which split the columns and rows and meet at barriers among
+ * themselves; a workgroup that cannot start while others run (a device
+ * shared with other streams) is left out once the first member has waited
+ * a short window (100 us by default), so the solve never waits for it.  The
+ * result does not depend on how many workgroups are members.
  */
 l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter, double tol,
                    double* x_out, const l0_opts* opts, l0_result* res_out, void* workspace,
                    size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Admission settings of the single-instance solve kernel (tests and tuning;
+ * process-wide, read when a solve is enqueued).
+ *   max_members  > 0: at most this many workgroups become members (the rest
+ *                leave at once); <= 0: no cap (one per compute unit)
+ *   window_us    > 0: how long the first member waits for the others before
+ *                closing admission; <= 0: the default, 100 us
+ * Results are the same for every setting; only the speed changes.
+ * Returns L0_OK.
+ */
+l0_status l0_set_solve_admission(int32_t max_members, int32_t window_us);
 
 /*
  * Batched decoding: many independent instances (each its own A, y, sizes,

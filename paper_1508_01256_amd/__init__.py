@@ -35,7 +35,7 @@ L0_TOL_RELATIVE, L0_TOL_ABSOLUTE = 0, 1
 
 #: every entry point declared in include/l0decode.h
 EXPORTED = ("l0_version", "l0_status_string", "l0_decode", "l0_workspace_bytes", "l0_decode_ex",
-            "l0_matrix_create", "l0_matrix_destroy", "l0_solve_workspace_bytes", "l0_solve",
+            "l0_matrix_create", "l0_matrix_destroy", "l0_solve_workspace_bytes", "l0_solve", "l0_set_solve_admission",
             "l0_batch_workspace_bytes", "l0_decode_batched", "l0_batch_autotune",
             "l0_server_create", "l0_server_submit", "l0_server_poll", "l0_server_drain",
             "l0_server_outstanding", "l0_server_destroy")
@@ -122,7 +122,9 @@ def lib():
         L.l0_server_drain.argtypes = [P]
         L.l0_server_outstanding.argtypes, L.l0_server_outstanding.restype = [P], I64
         L.l0_server_destroy.argtypes = [P]
+        L.l0_set_solve_admission.argtypes = [I32, I32]
         for f in ("l0_decode", "l0_decode_ex", "l0_matrix_create", "l0_matrix_destroy", "l0_solve",
+                  "l0_set_solve_admission",
                   "l0_decode_batched", "l0_batch_autotune", "l0_server_create", "l0_server_submit",
                   "l0_server_drain", "l0_server_destroy"):
             getattr(L, f).restype = ctypes.c_int
@@ -162,6 +164,12 @@ def l0_decode(col_idx, n, m, d, y, alpha, max_iter, tol, x_out, iters_out) -> in
 
 def l0_workspace_bytes(n, m, d, max_iter) -> int:
     return lib().l0_workspace_bytes(n, m, d, max_iter)
+
+
+def l0_set_solve_admission(max_members=0, window_us=0) -> int:
+    """Cap the solve kernel's member workgroups and set the admission
+    window (0 = defaults); results do not depend on either."""
+    return lib().l0_set_solve_admission(int(max_members), int(window_us))
 
 
 def _opts(rule, tol_mode, x_init, trace, tsize, timeline=None, weights=None):

@@ -194,6 +194,11 @@ extern "C" {
 
 const char* l0_version(void) { return "l0decode 0.1 (gfx950)"; }
 
+l0_status l0_set_solve_admission(int32_t max_members, int32_t window_us) {
+    l0::set_solve_admission(max_members, window_us);
+    return L0_OK;
+}
+
 const char* l0_status_string(int32_t code) {
     switch (code) {
         case 0: return "L0_OK / L0_CONVERGED";

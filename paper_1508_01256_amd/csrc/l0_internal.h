@@ -70,8 +70,10 @@ struct Ctrl {
     int support;             // columns ever updated
     int pad0;
     long long updates;       // sum of |T| over iterations
-    unsigned int start;      // start-up arrivals (every workgroup once)
-    int pad[23];
+    unsigned int start;      // start-up arrivals (every member once)
+    unsigned int admit;      // admission: registrations, kClosed once closed
+    unsigned int members;    // admitted workgroups, 0 until decided
+    int pad[21];
     unsigned int xcount[kMaxXcc];                 // workgroups resident on each XCD
     unsigned int xarrive[kMaxXcc * kXccStride];   // per-XCD barrier arrivals (monotonic)
     unsigned int xrelease[kMaxXcc * kXccStride];  // per-XCD release epoch
@@ -124,8 +126,13 @@ struct SolveParams {
 // Enqueue the matrix preparation (repack, range check, degree histogram, scan).
 hipError_t launch_prepare(const int32_t* col_idx, const MatrixView& A, int check, hipStream_t s);
 
-// Enqueue one solve (control reset + the persistent cooperative kernel).
+// Enqueue one solve (control reset + the persistent kernel).
 hipError_t launch_solve(const SolveParams& p, hipStream_t s);
+
+// Admission of the solve kernel's workgroups: at most max_members members
+// (0: no cap), admission closed by the first member after window_us
+// microseconds (<= 0: the default).
+void set_solve_admission(int32_t max_members, int32_t window_us);
 
 // Enqueue a fill of count int32 zeros (a kernel, so it may sit in graphs).
 hipError_t launch_zero(int32_t* p, int64_t count, hipStream_t s);

@@ -1,7 +1,10 @@
 // Device code of the Parallel-l0 decoder for gfx950.
 //
-// One solve is a single persistent, cooperatively launched kernel.  Each
-// iteration of Algorithm 2 runs as three grid-wide phases:
+// One solve is a single persistent kernel.  Its workgroups first admit
+// themselves as members (the ones running at start-up; the work is split
+// among the members only, so the grid barrier never waits for a workgroup
+// that could not become resident).  Each iteration of Algorithm 2 runs as
+// three phases over all members:
 //   vote     every column j is scored on the same residual r (eq.
 //            (selection_l0)); r is staged in LDS when 8m bytes fit, the
 //            column-index store is streamed in coalesced 16-byte loads;
@@ -13,9 +16,11 @@
 //            from the per-row change, counted with wave ballots;
 //   control  every workgroup reads the same counters and takes the same
 //            decision (converged / stalled / iteration cap).
-// Phases are separated by a grid barrier built on one monotonic counter.
+// Phases are separated by a barrier over the members built on monotonic
+// counters.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <climits>
 
 #include "l0_internal.h"
@@ -55,41 +60,92 @@ __device__ __forceinline__ bool wait_at_least(unsigned* p, unsigned target, Ctrl
     return true;
 }
 
-// Where this workgroup sits for the grid barrier.
+// Where this workgroup sits among the members and for the grid barrier.
 struct BarrierSite {
+    unsigned member;  // member id: 0 .. count-1
+    unsigned count;   // members
     unsigned xcc;     // its XCD
-    unsigned nx;      // workgroups on that XCD
-    unsigned nxcc;    // XCDs with at least one workgroup
+    unsigned nx;      // members on that XCD
+    unsigned nxcc;    // XCDs with at least one member
     unsigned epoch;   // barriers passed
 };
 
-// Start-up: every workgroup records its XCD, then waits (relaxed) for all to
-// have done so; the counts are final afterwards.
-__device__ bool barrier_setup(Ctrl* c, BarrierSite& b, uint64_t limit) {
-    __shared__ unsigned s_site[3];
-    __shared__ int s_ok;
+constexpr unsigned kClosed = 0x80000000u;  // admission closed (Ctrl::admit)
+
+// Start-up parameters of the solve kernel (wall-clock ticks).
+struct Admission {
+    uint64_t limit;   // bound of every wait (then the abort flag is raised)
+    uint64_t window;  // the first member closes admission this long after its start
+    unsigned cap;     // at most this many members
+};
+
+// Start-up.  Every workgroup registers on the admission word and takes the
+// registration number as its member id; ids below min(grid, cap) are
+// members, and a member records its XCD at once (during the launch ramp).
+// The member that completes the count publishes it.  If some workgroups
+// cannot start (the device is shared), the first member closes admission
+// `window` ticks after it started: the members are then the workgroups
+// registered by that time, and any later one finds admission closed and
+// leaves at once.  The members wait (relaxed) until all of them have
+// recorded their XCDs; every count is final afterwards.  Returns 1 for a
+// member, 0 for a workgroup turned away (it must leave without touching
+// anything), -1 when a wait timed out.  With a timeline, member 0 stamps its
+// start in entry 0.
+__device__ int admit(Ctrl* c, BarrierSite& b, unsigned cap, uint64_t window, uint64_t limit,
+                     int64_t* timeline) {
+    __shared__ unsigned s_site[5];
+    __shared__ int s_state;
     if (threadIdx.x == 0) {
-        const unsigned x = xcc_id();
-        __hip_atomic_fetch_add(&c->xcount[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&c->start, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int ok = wait_at_least(&c->start, gridDim.x, c, limit) ? 1 : 0;
-        unsigned nx = 0, nxcc = 0;
-        for (int i = 0; i < kMaxXcc; ++i) {
-            const unsigned v = __hip_atomic_load(&c->xcount[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            nxcc += v != 0;
-            if (i == static_cast<int>(x)) nx = v;
+        const uint64_t t0 = wall_clock64();
+        const unsigned want = min(gridDim.x, cap);
+        const unsigned id = __hip_atomic_fetch_add(&c->admit, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int state = (id < want) ? 1 : 0;  // id >= kClosed > want once closed
+        unsigned count = 0, x = 0, nx = 0, nxcc = 0;
+        if (state) {
+            if (timeline && id == 0) timeline[0] = static_cast<int64_t>(t0);
+            x = xcc_id();
+            __hip_atomic_fetch_add(&c->xcount[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the XCD count is in before the arrival
+            __hip_atomic_fetch_add(&c->start, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (id + 1 == want) {
+                __hip_atomic_store(&c->members, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (id == 0) {
+                while (__hip_atomic_load(&c->members, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                    if (wall_clock64() - t0 > window) {
+                        // registrations before the close are ids 0 .. v-1
+                        const unsigned v = __hip_atomic_fetch_or(&c->admit, kClosed, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&c->members, min(v & (kClosed - 1u), want), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            state = wait_at_least(&c->members, 1u, c, limit) ? 1 : -1;
+            count = __hip_atomic_load(&c->members, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (state == 1) state = wait_at_least(&c->start, count, c, limit) ? 1 : -1;
+            for (int i = 0; i < kMaxXcc; ++i) {
+                const unsigned v = __hip_atomic_load(&c->xcount[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                nxcc += v != 0;
+                if (i == static_cast<int>(x)) nx = v;
+            }
         }
-        s_site[0] = x;
-        s_site[1] = nx;
-        s_site[2] = nxcc;
-        s_ok = ok;
+        s_site[0] = id;
+        s_site[1] = count;
+        s_site[2] = x;
+        s_site[3] = nx;
+        s_site[4] = nxcc;
+        s_state = state;
     }
     __syncthreads();
-    b.xcc = s_site[0];
-    b.nx = s_site[1];
-    b.nxcc = s_site[2];
+    b.member = s_site[0];
+    b.count = s_site[1];
+    b.xcc = s_site[2];
+    b.nx = s_site[3];
+    b.nxcc = s_site[4];
     b.epoch = 0;
-    return s_ok != 0;
+    return s_state;
 }
 
 // Grid barrier, hierarchical over XCDs.  Each workgroup drains its own memory
@@ -122,7 +178,7 @@ __device__ bool grid_sync(Ctrl* c, BarrierSite& b, uint64_t limit, int64_t* time
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         s_ok = ok;
-        if (timeline && blockIdx.x == 0) timeline[b.epoch] = static_cast<int64_t>(wall_clock64());
+        if (timeline && b.member == 0) timeline[b.epoch] = static_cast<int64_t>(wall_clock64());
     }
     __syncthreads();
     return s_ok != 0;
@@ -284,13 +340,14 @@ __device__ __forceinline__ void filter_chunk(const SolveParams& p, const uint32_
 // this pass.
 template <int D, bool COMPACT>
 __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32_t* lds_w,
-                           int* q_items, int* q_count, int* q_ovf, int pos) {
+                           int* q_items, int* q_count, int* q_ovf, int pos, unsigned member,
+                           unsigned members) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t nchunks = static_cast<uint32_t>(p.ntiles) * Chunk<COMPACT>::kPerTile;
     const uint32_t n = static_cast<uint32_t>(p.n);
     const uint32_t* __restrict__ words = COMPACT ? lds_w : p.rword;
-    const uint32_t stride = gridDim.x * kWaves;
-    const uint32_t first = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const uint32_t stride = members * kWaves;
+    const uint32_t first = member * kWaves + (threadIdx.x >> 6);
     // prefetches past the last chunk read the last chunk again (an L2 hit;
     // unconditional loads keep the waits exact)
     const uint32_t last = nchunks - 1;
@@ -308,7 +365,7 @@ __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32
         g += stride;
     }
     __syncthreads();
-    if (p.timeline && blockIdx.x == 0 && threadIdx.x == 0)
+    if (p.timeline && member == 0 && threadIdx.x == 0)
         p.timeline[3 * p.max_iter + 9 + 3 * l] = static_cast<int64_t>(wall_clock64());
     if (*q_ovf == 0) {
         const int cnt = *q_count;
@@ -334,7 +391,7 @@ __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32
     if (threadIdx.x == 0) {
         *q_count = 0;
         *q_ovf = 0;
-        if (p.timeline && blockIdx.x == 0)
+        if (p.timeline && member == 0)
             p.timeline[3 * p.max_iter + 10 + 3 * l] = static_cast<int64_t>(wall_clock64());
     }
 }
@@ -354,22 +411,25 @@ struct Occ {
 };
 
 template <int D, bool COMPACT>
-__global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(SolveParams p, uint64_t limit) {
+__global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(SolveParams p, Admission adm) {
     extern __shared__ uint32_t lds_w[];
     __shared__ int q_items[kQueue];
     __shared__ int q_count, q_ovf;
     if (threadIdx.x == 0) q_count = q_ovf = 0;
     const int tid = threadIdx.x;
-    const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
-    const int64_t gsize = static_cast<int64_t>(gridDim.x) * kBlock;
     Ctrl* c = p.ctrl;
-    if (p.timeline && blockIdx.x == 0 && tid == 0) p.timeline[0] = static_cast<int64_t>(wall_clock64());
+    const uint64_t limit = adm.limit;
     BarrierSite site;
-    if (!barrier_setup(c, site, limit)) {
+    const int state = admit(c, site, adm.cap, adm.window, limit, p.timeline);
+    if (state == 0) return;  // not admitted: the members do all the work
+    // work is split by member id over the members
+    const int64_t gtid = static_cast<int64_t>(site.member) * kBlock + tid;
+    const int64_t gsize = static_cast<int64_t>(site.count) * kBlock;
+    if (state < 0) {
         if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
         return;
     }
-    if (p.timeline && blockIdx.x == 0 && tid == 0)
+    if (p.timeline && site.member == 0 && tid == 0)
         p.timeline[3 * p.max_iter + 7] = static_cast<int64_t>(wall_clock64());
 
     // Without a resume vector and with the bucket words in LDS (y then has
@@ -553,9 +613,9 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             for (int t = (m4 << 2) + tid; t < p.m; t += kBlock) lds_w[t] = p.rword[t];
             __syncthreads();
         }
-        if (p.timeline && blockIdx.x == 0 && tid == 0)
+        if (p.timeline && site.member == 0 && tid == 0)
             p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
-        vote_phase<D, COMPACT>(p, l, tau, lds_w, q_items, &q_count, &q_ovf, pos);
+        vote_phase<D, COMPACT>(p, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member, site.count);
         if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
             return;
@@ -793,13 +853,23 @@ hipError_t launch_zero(int32_t* p, int64_t count, hipStream_t s) {
 
 namespace {
 
-uint64_t barrier_limit_ticks() {
+uint64_t clock_khz() {
     int dev = 0, khz = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
         khz = 100000;  // 100 MHz
-    return static_cast<uint64_t>(khz) * 1000ull * 20ull;  // 20 seconds
+    return static_cast<uint64_t>(khz);
 }
+
+uint64_t barrier_limit_ticks() { return clock_khz() * 1000ull * 20ull; }  // 20 seconds
+
+// Admission settings (process-wide): member cap (0: none) and the window in
+// microseconds.  All workgroups of an idle device start within a few
+// microseconds, and the last of them closes admission at once; the window
+// only matters when some cannot start.
+constexpr int kAdmitWindowUs = 100;
+std::atomic<int> g_admit_cap{0};
+std::atomic<int> g_admit_window_us{kAdmitWindowUs};
 
 template <int D>
 hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s) {
@@ -868,10 +938,17 @@ hipError_t solve_d(const SolveParams& p, hipStream_t s) {
                            static_cast<int64_t>(2 * (p.max_iter + 2)));
     }
     SolveParams q = p;
-    uint64_t limit = barrier_limit_ticks();
-    void* args[] = {&q, &limit};
-    return hipLaunchCooperativeKernel(fn, dim3(static_cast<unsigned>(grid)), dim3(kBlock), args,
-                                      static_cast<unsigned>(lds), s);
+    Admission adm;
+    adm.limit = barrier_limit_ticks();
+    adm.window = clock_khz() * static_cast<uint64_t>(g_admit_window_us.load()) / 1000ull;
+    const int cap = g_admit_cap.load();
+    adm.cap = cap > 0 ? static_cast<unsigned>(cap) : 0xFFFFFFFFu;
+    void* args[] = {&q, &adm};
+    // An ordinary launch: the kernel admits the workgroups that start and
+    // splits the work among them, so co-residency of the whole grid is not
+    // required (a cooperative launch would add about 20 us per solve).
+    return hipLaunchKernel(fn, dim3(static_cast<unsigned>(grid)), dim3(kBlock), args,
+                           static_cast<unsigned>(lds), s);
 }
 
 template <int D>
@@ -909,5 +986,10 @@ hipError_t launch_prepare(const int32_t* col_idx, const MatrixView& A, int /*che
 hipError_t launch_solve(const SolveParams& p, hipStream_t s) { return solve_dispatch(p, s); }
 
 uint64_t wait_limit_ticks() { return barrier_limit_ticks(); }
+
+void set_solve_admission(int32_t max_members, int32_t window_us) {
+    g_admit_cap.store(max_members > 0 ? max_members : 0);
+    g_admit_window_us.store(window_us > 0 ? window_us : kAdmitWindowUs);
+}
 
 }  // namespace l0
