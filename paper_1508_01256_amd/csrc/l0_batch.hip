@@ -380,23 +380,56 @@ __device__ void wg_sort(Ptr buf, int cnt) {
     }
 }
 
+// At most this many entries appended since a long list was last sorted are
+// merged into its sorted prefix by rank; more are sorted from scratch.
+constexpr int kMergeNew = 256;
+
 // row_residual for one row with a long support list, computed by the whole
 // workgroup (every thread calls it; the result is valid in thread 0): the
 // list is sorted (in LDS when it fits, else in place) when it has unsorted
 // entries, then the column terms are gathered 512 entries at a time into LDS
-// and thread 0 adds them in ascending j from +0.0.
+// and thread 0 adds them in ascending j from +0.0.  A list in LDS whose
+// sorted prefix has a few new entries after it is merged instead: the
+// column ids are distinct, so entry v goes to position (prefix entries
+// below v) + (new entries below v), one thread per entry.
 __device__ double long_row_residual(const BlockState& s, const Lds& L, int i) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int cnt = s.slot_cnt[i];
     const auto list = s.slots + s.row_off[i];
-    const bool sorted = s.slot_sorted[i] == cnt;
+    const int done = s.slot_sorted[i];
+    const bool sorted = done == cnt;
     const bool in_lds = cnt <= kLongList;
     const lptr<int> sb = L.queue;
     const lptr<double> xb = (lptr<double>)(L.queue + kLongList);
     if (in_lds) {
         for (int t = tid; t < cnt; t += nthr) sb[t] = list[t];
         __syncthreads();
-        if (!sorted) {
+        if (!sorted && done > 0 && cnt - done <= kMergeNew) {
+            const lptr<int> db = (lptr<int>)xb;  // kLongList ints, free until the gather
+            for (int t = tid; t < cnt; t += nthr) {
+                const int v = sb[t];
+                int below = 0;
+                for (int u = done; u < cnt; ++u) below += sb[u] < v;
+                if (t < done) {
+                    below += t;
+                } else {
+                    int lo = 0, hi = done;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (sb[mid] < v) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    below += lo;
+                }
+                db[below] = v;
+            }
+            __syncthreads();
+            for (int t = tid; t < cnt; t += nthr) {
+                const int v = db[t];
+                sb[t] = v;
+                list[t] = v;
+            }
+        } else if (!sorted) {
             wg_sort<false>(sb, cnt);
             for (int t = tid; t < cnt; t += nthr) list[t] = sb[t];
         }

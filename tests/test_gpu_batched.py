@@ -183,6 +183,19 @@ def test_long_support_lists():
     assert res[2]["support_size"] == g["support_size"]
 
 
+def test_long_lists_growing_over_many_iterations():
+    """Instances of the sweep workload with m of 11 to 94 that run to
+    max_iter: columns keep entering the support, so long row lists get a few
+    new entries after their sorted prefix in most iterations (merged by rank
+    into the prefix)."""
+    params = gen.sweep_params(4096)
+    insts = [gen.make_instance(params[q]["seed"], params[q]["n"], params[q]["m"], params[q]["d"],
+                               params[q]["k"]) for q in (1734, 118, 2425, 3803, 1482, 3481)]
+    res = batched_run(insts)
+    check_all(insts, res, "growing-lists")
+    assert sum(r["outcome"] == l0.L0_MAX_ITER for r in res) >= 4
+
+
 def test_teams_on_large_instances():
     """Instances with more than 2^19 column indices are decoded by teams of
     workgroups (here 14, 6 and the cap of 32, one with bucket words in global
