@@ -208,7 +208,8 @@ size_t l0_solve_workspace_bytes(l0_matrix A, int32_t max_iter);
  * themselves; a workgroup that cannot start while others run (a device
  * shared with other streams) is left out once the first member has waited
  * a short window (100 us by default), so the solve never waits for it.  The
- * result does not depend on how many workgroups are members.
+ * result does not depend on how many workgroups are members, and solves on
+ * several streams of one device may overlap (each with its own workspace).
  */
 l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter, double tol,
                    double* x_out, const l0_opts* opts, l0_result* res_out, void* workspace,

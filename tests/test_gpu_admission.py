@@ -89,3 +89,44 @@ def test_full_size_with_a_short_window():
     l0.l0_set_solve_admission(0, 0)
     u = gpu_run(inst.n, inst.m, inst.d, inst.col_idx, inst.y, inst.alpha)
     assert np.array_equal(u["x"], g["x"]) and u["trace"].tolist() == g["trace"].tolist()
+
+
+def test_concurrent_solves_on_two_streams():
+    """Two one-shot decodes in flight on two streams at once, eight times over:
+    each solve's workgroups compete with the other's for the compute units,
+    so a solve may close admission with only the workgroups that got one.
+    Every result equals the same decode run alone."""
+    a = gen.make_instance(9500, 1 << 20, 10486, 7, 1000)
+    b = gen.make_instance(9501, 600000, 30000, 5, 2500)
+    dev = "cuda"
+
+    def upload(i):
+        return (torch.from_numpy(i.col_idx).to(dev), torch.from_numpy(i.y).to(dev),
+                torch.empty(l0.l0_workspace_bytes(i.n, i.m, i.d, 100), dtype=torch.uint8, device=dev))
+
+    (ca, ya, wa), (cb, yb, wb) = upload(a), upload(b)
+    ref = {}
+    for name, i, c, y, w in (("a", a, ca, ya, wa), ("b", b, cb, yb, wb)):
+        x = torch.empty(i.n, dtype=torch.float64, device=dev)
+        r = l0.new_result(dev)
+        assert l0.l0_decode_ex(c, i.n, i.m, i.d, y, i.alpha, 100, 1e-10, x, None, r, w) == l0.L0_OK
+        torch.cuda.synchronize()
+        ref[name] = (x.cpu(), r.cpu())
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    torch.cuda.synchronize()
+    for rep in range(8):
+        xa, ra = torch.empty(a.n, dtype=torch.float64, device=dev), l0.new_result(dev)
+        xb, rb = torch.empty(b.n, dtype=torch.float64, device=dev), l0.new_result(dev)
+        with torch.cuda.stream(s1):
+            assert l0.l0_decode_ex(ca, a.n, a.m, a.d, ya, a.alpha, 100, 1e-10, xa, None, ra, wa) == l0.L0_OK
+        with torch.cuda.stream(s2):
+            assert l0.l0_decode_ex(cb, b.n, b.m, b.d, yb, b.alpha, 100, 1e-10, xb, None, rb, wb) == l0.L0_OK
+        outs.append((xa, ra, xb, rb))
+    torch.cuda.synchronize()
+    say("concurrent solves done")
+    for xa, ra, xb, rb in outs:
+        assert torch.equal(ra.cpu(), ref["a"][1]) and torch.equal(xa.cpu(), ref["a"][0])
+        assert torch.equal(rb.cpu(), ref["b"][1]) and torch.equal(xb.cpu(), ref["b"][0])
+    o = oracle_run(a.n, a.m, a.d, a.col_idx, a.y, a.alpha)
+    assert np.array_equal(ref["a"][0].numpy(), o["x"])
