@@ -237,3 +237,14 @@ def test_full_size_workloads(name, kind):
     say("full", name, kind)
     g, o = run_both(inst)
     assert_parity(g, o, label=f"{name}/{kind}")
+
+
+def test_index_store_past_two_gigabytes():
+    """n = 2^27 columns of degree 5: 2.7 GB of 32-bit column indices (byte
+    offsets past 2^31) and m = 2^20 rows (32-bit repacked rows, bucket words
+    read from global memory), decoded bitwise as the oracle does."""
+    inst = gen.make_instance(9700, 1 << 27, 1 << 20, 5, 20000)
+    say("index store past 2 GB", inst.n, inst.m, inst.d)
+    g, o = run_both(inst)
+    assert_parity(g, o, label="n2^27 d5")
+    assert o["outcome"] == l0.L0_CONVERGED
