@@ -450,6 +450,82 @@ __device__ double long_row_residual(const BlockState& s, const Lds& L, int i) {
     return s.y[i] - sum;
 }
 
+// Support lists of at most this many entries are summed by one wave.
+constexpr int kWaveList = 256;
+
+// Ascending bitonic sort of kWaveList ints held by one wave, entry e in
+// v[e / 64] of lane e % 64; pairs one register apart are exchanged within
+// the lane, pairs within a register across lanes.
+__device__ __forceinline__ void wave_sort(int (&v)[kWaveList / 64]) {
+    constexpr int K = kWaveList / 64;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int size = 2; size <= kWaveList; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= 64) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int kp = k ^ (stride >> 6);
+                    if (kp > k) {
+                        const bool up = ((k * 64 + lane) & size) == 0;
+                        const int a = v[k], b = v[kp];
+                        v[k] = up ? min(a, b) : max(a, b);
+                        v[kp] = up ? max(a, b) : min(a, b);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int other = __shfl_xor(v[k], stride);
+                    const bool up = ((k * 64 + lane) & size) == 0;
+                    const bool lower = (lane & stride) == 0;
+                    v[k] = (lower == up) ? min(v[k], other) : max(v[k], other);
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b & 0xFFFFFFFFu), l));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), l));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// row_residual for one row whose support list has at most kWaveList
+// entries, computed by one wave (every lane calls it; the result is valid in
+// every lane): the list is sorted in registers (and written back) when it
+// has unsorted entries, each lane gathers the column terms of its entries,
+// and the terms are added in ascending j from +0.0, lane by lane.
+__device__ __noinline__ double wave_row_residual(const BlockState& s, int i) {
+    constexpr int K = kWaveList / 64;
+    const int lane = threadIdx.x & 63;
+    const int cnt = s.slot_cnt[i];
+    const auto list = s.slots + s.row_off[i];
+    int v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = k * 64 + lane < cnt ? list[k * 64 + lane] : INT_MAX;
+    if (s.slot_sorted[i] != cnt) {
+        wave_sort(v);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (k * 64 + lane < cnt) list[k * 64 + lane] = v[k];
+        if (lane == 0) s.slot_sorted[i] = cnt;
+    }
+    double xv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) xv[k] = k * 64 + lane < cnt ? column_term(s, v[k]) : 0.0;
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int len = min(64, cnt - k * 64);
+        for (int l = 0; l < len; ++l) sum += read_lane(xv[k], l);
+    }
+    return s.y[i] - sum;
+}
+
 // The outcome is written last, after a system-scope fence: a host polling
 // results in host-mapped memory sees a complete record (and a finished
 // x_hat) once the outcome is no longer the value it stored there.
@@ -681,8 +757,9 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         empty = 0;
 
         // residual update of the touched rows, split over the team; short
-        // support lists one row per thread, long ones by this whole
-        // workgroup afterwards; ||r||_0 by its change
+        // support lists one row per thread, longer ones one row per wave
+        // afterwards, the longest by this whole workgroup; ||r||_0 by its
+        // change
         const int na = load_agent(&ring->affc);
         const int long_cap = (nthr >> 6) * 64;
         const lptr<int> long_rows = L.queue + kBatchQueue;
@@ -700,8 +777,19 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         }
         __syncthreads();
         const int nl = min(L.ctr[0], long_cap);
+        for (int li = tid >> 6; li < nl; li += nthr >> 6) {
+            const int i = long_rows[li];
+            if (s.slot_cnt[i] > kWaveList) continue;  // uniform across the wave
+            const double rn = wave_row_residual(s, i);
+            if ((tid & 63) == 0) {
+                delta += finish_row(s, L, wm, i, rn, tau, inv_w);
+                long_rows[li] = -1;
+            }
+        }
+        __syncthreads();
         for (int li = 0; li < nl; ++li) {
             const int i = long_rows[li];
+            if (i < 0) continue;  // done by a wave (uniform across the workgroup)
             const double rn = long_row_residual(s, L, i);
             if (tid == 0) delta += finish_row(s, L, wm, i, rn, tau, inv_w);
         }
