@@ -210,6 +210,8 @@ size_t l0_solve_workspace_bytes(l0_matrix A, int32_t max_iter);
  * a short window (100 us by default), so the solve never waits for it.  The
  * result does not depend on how many workgroups are members, and solves on
  * several streams of one device may overlap (each with its own workspace).
+ * A solve enqueues kernels only (no memset, no allocation with a caller
+ * workspace), so it may be captured in a HIP graph and replayed.
  */
 l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter, double tol,
                    double* x_out, const l0_opts* opts, l0_result* res_out, void* workspace,
