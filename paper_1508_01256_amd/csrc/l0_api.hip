@@ -133,9 +133,18 @@ void carve_solve(l0::SolveParams& q, char* base, int64_t n, int32_t m, int32_t d
     q.slots = reinterpret_cast<int32_t*>(p);
 }
 
+// The control-block run that a one-shot decode's preparation clears for the
+// solve whose workspace starts at ws (none when the solve must fill it).
+l0::ZeroSpan one_shot_clear(char* ws, int64_t n, int32_t m, int32_t d, int32_t max_iter) {
+    l0::SolveParams q{};
+    q.max_iter = max_iter;
+    carve_solve(q, ws, n, m, d, max_iter);
+    return l0::solve_control_span(q);
+}
+
 l0_status run_solve(const l0::MatrixView& A, const double* y, double alpha, int32_t max_iter,
                     double tol, double* x_out, const l0_opts* opts, l0_result* res,
-                    int32_t* iters_out, char* ws, hipStream_t stream) {
+                    int32_t* iters_out, char* ws, hipStream_t stream, bool ctrl_cleared = false) {
     l0::SolveParams q{};
     q.n = A.n;
     q.m = A.m;
@@ -160,6 +169,7 @@ l0_status run_solve(const l0::MatrixView& A, const double* y, double alpha, int3
     q.res = res;
     q.iters_out = iters_out;
     carve_solve(q, ws, A.n, A.m, A.d, max_iter);
+    q.ctrl_cleared = ctrl_cleared ? 1 : 0;
     return from_hip(l0::launch_solve(q, stream));
 }
 
@@ -233,10 +243,11 @@ l0_status l0_decode_ex(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, 
     if (!buffer_ok(workspace, need)) return L0_ERR_ARG;
     char* base = static_cast<char*>(workspace);
     const l0::MatrixView A = carve_matrix(base, n, m, d);
-    l0_status st = from_hip(l0::launch_prepare(col_idx, A, 1, stream));
+    char* const sws = base + l0::matrix_layout(n, m, d).total;
+    const l0::ZeroSpan clear = one_shot_clear(sws, n, m, d, max_iter);
+    l0_status st = from_hip(l0::launch_prepare(col_idx, A, 1, stream, clear));
     if (st != L0_OK) return st;
-    return run_solve(A, y, alpha, max_iter, tol, x_out, opts, res_out, nullptr,
-                     base + l0::matrix_layout(n, m, d).total, stream);
+    return run_solve(A, y, alpha, max_iter, tol, x_out, opts, res_out, nullptr, sws, stream, clear.p != nullptr);
 }
 
 l0_status l0_decode(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y,
@@ -254,9 +265,11 @@ l0_status l0_decode(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, con
     char* base = static_cast<char*>(ws);
     const l0::MatrixView A = carve_matrix(base, n, m, d);
     l0_result* res = reinterpret_cast<l0_result*>(base + need - l0::align256(sizeof(l0_result)));
-    l0_status st = from_hip(l0::launch_prepare(col_idx, A, 1, stream));
+    const l0::ZeroSpan clear = one_shot_clear(base + mat, n, m, d, max_iter);
+    l0_status st = from_hip(l0::launch_prepare(col_idx, A, 1, stream, clear));
     if (st == L0_OK)
-        st = run_solve(A, y, alpha, max_iter, tol, x_out, nullptr, res, iters_out, base + mat, stream);
+        st = run_solve(A, y, alpha, max_iter, tol, x_out, nullptr, res, iters_out, base + mat, stream,
+                       clear.p != nullptr);
     e = hipFreeAsync(ws, stream);
     if (st == L0_OK && e != hipSuccess) st = from_hip(e);
     return st;

@@ -121,10 +121,26 @@ struct SolveParams {
     int32_t* aff_list;
     uint32_t* member;
     int32_t* slots;
+    // the control block and counters are already zero (a one-shot decode
+    // has the preparation clear them), so the solve launches no fill
+    int32_t ctrl_cleared;
 };
 
-// Enqueue the matrix preparation (repack, range check, degree histogram, scan).
-hipError_t launch_prepare(const int32_t* col_idx, const MatrixView& A, int check, hipStream_t s);
+// A run of int32 words to zero, or none (p == nullptr).
+struct ZeroSpan {
+    int32_t* p = nullptr;
+    int64_t count = 0;
+};
+
+// The solve's control block and per-iteration counters as one run of words,
+// when they are adjacent and the run is short enough for the scan kernel to
+// clear (one-shot decodes); none otherwise.
+ZeroSpan solve_control_span(const SolveParams& p);
+
+// Enqueue the matrix preparation (repack, range check, degree histogram,
+// scan); the scan kernel also zeroes `clear`.
+hipError_t launch_prepare(const int32_t* col_idx, const MatrixView& A, int check, hipStream_t s,
+                          ZeroSpan clear = ZeroSpan());
 
 // Enqueue one solve (control reset + the persistent kernel).
 hipError_t launch_solve(const SolveParams& p, hipStream_t s);

@@ -775,10 +775,12 @@ constexpr int kScanPer = 12;
 constexpr int kScanChunk = 1024 * kScanPer;
 __device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
 
-__global__ void __launch_bounds__(1024) scan_kernel(MatrixView A) {
+__global__ void __launch_bounds__(1024) scan_kernel(MatrixView A, int32_t* clear, int64_t clear_count) {
     __shared__ int s_val[kScanChunk + kScanChunk / 32];
     __shared__ int s_wave[16];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // a one-shot decode's solve control block (read only by the next kernel)
+    for (int64_t i = tid; i < clear_count; i += 1024) clear[i] = 0;
     int carry = 0;
     for (int base = 0; base < A.m; base += kScanChunk) {
         const int len = min(kScanChunk, A.m - base);
@@ -872,7 +874,7 @@ std::atomic<int> g_admit_cap{0};
 std::atomic<int> g_admit_window_us{kAdmitWindowUs};
 
 template <int D>
-hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s) {
+hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s, ZeroSpan clear) {
     const int cus = device_cus();
     // the degree counts and the bad-index flag follow each other in the
     // matrix buffers: one fill clears both
@@ -902,7 +904,7 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s)
     void* args[] = {const_cast<int32_t**>(&col_idx), const_cast<MatrixView*>(&A)};
     hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(blocks)), dim3(1024), args, lds, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, A);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, A, clear.p, clear.count);
     return hipGetLastError();
 }
 
@@ -928,7 +930,9 @@ hipError_t solve_d(const SolveParams& p, hipStream_t s) {
     // control block and per-iteration counters (adjacent in the workspace:
     // one fill clears both)
     int32_t* const ctrl_ints = reinterpret_cast<int32_t*>(p.ctrl);
-    if (p.tcount >= ctrl_ints + sizeof(Ctrl) / sizeof(int32_t) && p.tcount - ctrl_ints <= 4096) {
+    if (p.ctrl_cleared) {
+        // zeroed by the preparation's scan kernel, earlier on this stream
+    } else if (p.tcount >= ctrl_ints + sizeof(Ctrl) / sizeof(int32_t) && p.tcount - ctrl_ints <= 4096) {
         hipLaunchKernelGGL(zero_ints, dim3(8), dim3(256), 0, s, ctrl_ints,
                            static_cast<int64_t>(p.tcount - ctrl_ints) + 2 * (p.max_iter + 2));
     } else {
@@ -958,12 +962,13 @@ hipError_t solve_dispatch_r(const SolveParams& p, hipStream_t s) {
 }
 
 template <int D = kDMin>
-hipError_t prepare_dispatch(int d, const int32_t* col_idx, const MatrixView& A, hipStream_t s) {
+hipError_t prepare_dispatch(int d, const int32_t* col_idx, const MatrixView& A, hipStream_t s,
+                            ZeroSpan clear) {
     if constexpr (D > kDMax) {
         return hipErrorInvalidValue;
     } else {
-        if (d == D) return prepare_d<D>(col_idx, A, s);
-        return prepare_dispatch<D + 1>(d, col_idx, A, s);
+        if (d == D) return prepare_d<D>(col_idx, A, s, clear);
+        return prepare_dispatch<D + 1>(d, col_idx, A, s, clear);
     }
 }
 
@@ -979,8 +984,25 @@ hipError_t solve_dispatch(const SolveParams& p, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_prepare(const int32_t* col_idx, const MatrixView& A, int /*check*/, hipStream_t s) {
-    return prepare_dispatch(A.d, col_idx, A, s);
+hipError_t launch_prepare(const int32_t* col_idx, const MatrixView& A, int /*check*/, hipStream_t s,
+                          ZeroSpan clear) {
+    return prepare_dispatch(A.d, col_idx, A, s, clear);
+}
+
+ZeroSpan solve_control_span(const SolveParams& p) {
+    // the one-fill case of the solve's own reset, bounded so that one
+    // workgroup clears it in a few microseconds
+    constexpr int64_t kMaxWords = int64_t(1) << 16;
+    int32_t* const ctrl_ints = reinterpret_cast<int32_t*>(p.ctrl);
+    ZeroSpan z;
+    if (p.tcount >= ctrl_ints + sizeof(Ctrl) / sizeof(int32_t) && p.tcount - ctrl_ints <= 4096) {
+        const int64_t count = static_cast<int64_t>(p.tcount - ctrl_ints) + 2 * (static_cast<int64_t>(p.max_iter) + 2);
+        if (count <= kMaxWords) {
+            z.p = ctrl_ints;
+            z.count = count;
+        }
+    }
+    return z;
 }
 
 hipError_t launch_solve(const SolveParams& p, hipStream_t s) { return solve_dispatch(p, s); }
