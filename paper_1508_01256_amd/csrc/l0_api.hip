@@ -467,16 +467,14 @@ bool plan_batch(const l0_problem* probs, int32_t count, int block_threads, int w
             std::max<int64_t>(1, static_cast<int64_t>(per_cu) * (cus > 0 ? cus : 1) / std::max(1, share));
         // Estimated cost of an instance: its column indices, three times over
         // when its bucket words do not fit in LDS even folded to 16 bits (the
-        // vote then gathers them from global memory, about three times slower).  The group's
-        // instances are claimed most costly first, and an instance gets one
-        // team member per unit of cost (at most kMaxTeam, never more than the
-        // resident workgroups: members wait for each other).
+        // vote then gathers them from global memory, about three times
+        // slower).  An instance gets one team member per unit of cost (at
+        // most kMaxTeam, never more than the resident workgroups: members
+        // wait for each other).
         auto cost = [&](int32_t i) {
             const int64_t nd = probs[i].n * probs[i].d;
             return probs[i].m <= 2 * static_cast<int64_t>(g.words_cap) ? nd : 3 * nd;
         };
-        std::stable_sort(pl.order.begin() + g.inst_start, pl.order.begin() + g.inst_start + g.inst_count,
-                         [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
         const int64_t tmax = std::min<int64_t>(l0::kMaxTeam, resident);
         // A batch too small to fill the resident workgroups at kTeamUnit per
         // member (a few requests of a server, one large instance) gets a
@@ -484,12 +482,22 @@ bool plan_batch(const l0_problem* probs, int32_t count, int block_threads, int w
         int64_t total = 0;
         for (int32_t q = g.inst_start; q < g.inst_start + g.inst_count; ++q) total += cost(pl.order[q]);
         const int64_t unit = std::max<int64_t>(kMinTeamUnit, std::min<int64_t>(kTeamUnit, total / resident));
+        for (int32_t q = g.inst_start; q < g.inst_start + g.inst_count; ++q) {
+            const int32_t i = pl.order[q];
+            pl.team[i] = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(tmax, (cost(i) + unit - 1) / unit)));
+        }
+        // Claim order: largest cost per team member first (it sets the time
+        // of an iteration, and an instance of unforeseen iteration count is
+        // then long for that reason), larger total cost first among equals.
+        std::stable_sort(pl.order.begin() + g.inst_start, pl.order.begin() + g.inst_start + g.inst_count,
+                         [&](int32_t a, int32_t b) {
+                             const int64_t pa = cost(a) / pl.team[a], pb = cost(b) / pl.team[b];
+                             return pa != pb ? pa > pb : cost(a) > cost(b);
+                         });
         g.item_start = static_cast<int32_t>(pl.items.size());
         for (int32_t q = g.inst_start; q < g.inst_start + g.inst_count; ++q) {
             const int32_t i = pl.order[q];
-            const int t = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(tmax, (cost(i) + unit - 1) / unit)));
-            pl.team[i] = t;
-            for (int r = 0; r < t; ++r) pl.items.push_back(i | (r << l0::kItemInstBits));
+            for (int r = 0; r < pl.team[i]; ++r) pl.items.push_back(i | (r << l0::kItemInstBits));
         }
         g.item_count = static_cast<int32_t>(pl.items.size()) - g.item_start;
         g.grid = static_cast<int>(std::min<int64_t>(resident, g.item_count));
