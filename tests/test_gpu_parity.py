@@ -248,3 +248,25 @@ def test_index_store_past_two_gigabytes():
     g, o = run_both(inst)
     assert_parity(g, o, label="n2^27 d5")
     assert o["outcome"] == l0.L0_CONVERGED
+
+
+@pytest.mark.parametrize("max_iter", [100, 40000])
+def test_one_shot_control_reset_paths(max_iter):
+    """A one-shot decode has its preparation clear the solve's control block
+    and counters when they form a short run; with max_iter = 40000 the
+    counters are too long for that and the solve fills them itself.  Both
+    paths, twice in a row on one workspace (the second call must not see the
+    first one's counters), against the oracle."""
+    inst = gen.make_instance(9900, 50000, 5000, 7, 300)
+    col = to_dev(inst.col_idx, torch.int32)
+    y = to_dev(inst.y, torch.float64)
+    ws = torch.empty(l0.l0_workspace_bytes(inst.n, inst.m, inst.d, max_iter), dtype=torch.uint8, device="cuda")
+    o = oracle_run(inst.n, inst.m, inst.d, inst.col_idx, inst.y, inst.alpha, max_iter=max_iter)
+    for rep in range(2):
+        x = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+        res = l0.new_result()
+        assert l0.l0_decode_ex(col, inst.n, inst.m, inst.d, y, inst.alpha, max_iter, 1e-10, x, None, res, ws) == l0.L0_OK
+        torch.cuda.synchronize()
+        r = l0.results_list(res.view(1, 3))[0]
+        assert r["outcome"] == o["outcome"] and r["iters"] == o["iters"], (max_iter, rep, r)
+        assert np.array_equal(x.cpu().numpy(), o["x"]), (max_iter, rep)
