@@ -18,49 +18,69 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "l0_oracle.c")
 _LIB = os.path.join(_HERE, "libl0oracle.so")
+_LIB_OMP = os.path.join(_HERE, "libl0oracle_omp.so")
 
 RULE_L0DEC = 0
 RULE_MODE = 1
 RULE_SHIFTED_L0DEC = 2  # Algorithm 3: one candidate per column per pass
 RULE_SHIFTED_MODE = 3
+TOL_RELATIVE, TOL_ABSOLUTE = 0, 1  # tau = tol * max_i |y_i|, or tau = tol
 CONVERGED, STALLED, MAX_ITER = 0, 1, 2
 OUTCOME_NAMES = {CONVERGED: "CONVERGED", STALLED: "STALLED", MAX_ITER: "MAX_ITER"}
 
 
 def build(force: bool = True) -> str:
-    """Compile ``libl0oracle.so`` with gcc (-O2, no FP contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-               "-std=c11", "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
+    """Compile ``libl0oracle.so`` (single-threaded) and ``libl0oracle_omp.so``
+    (the same source with OpenMP) with gcc (-O2, no FP contraction, no
+    fast-math)."""
+    for lib, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+            cmd = ["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+                   "-std=c11", "-Wall", "-Wextra", "-Wno-unknown-pragmas", *extra, "-o", lib + ".tmp", _SRC,
+                   "-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(lib + ".tmp", lib)
     return _LIB
 
 
 _lib = None
+_lib_omp = None
 
 
-def _load():
-    global _lib
+def _load(threads: bool = False):
+    """The single-threaded oracle library, or with threads=True its OpenMP
+    build (same source, same results)."""
+    global _lib, _lib_omp
+    if threads:
+        if _lib_omp is None:
+            if not os.path.exists(_LIB_OMP):
+                build(force=False)
+            _lib_omp = _declare(ctypes.CDLL(_LIB_OMP))
+        return _lib_omp
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
-        P, I32, I64, F64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-        lib.orc_parallel_l0.argtypes = [I64, I32, I32, P, P, F64, I32, I32, F64, P, P, P, P, P, P, P, P]
-        lib.orc_parallel_l0.restype = ctypes.c_int
-        lib.orc_serial_l0.argtypes = [I64, I32, I32, P, P, F64, I32, I32, F64, P, P, P, P, P]
-        lib.orc_serial_l0.restype = ctypes.c_int
-        lib.orc_residual.argtypes = [I64, I32, I32, P, P, P, P, P]
-        lib.orc_residual.restype = None
-        lib.orc_score_columns.argtypes = [I64, I32, P, P, F64, I32, I32, P, P, P]
-        lib.orc_score_columns.restype = None
-        lib.orc_score_columns_shifted.argtypes = [I64, I32, P, P, F64, I32, I32, I32, P, P]
-        lib.orc_score_columns_shifted.restype = None
-        lib.orc_literal_decrease.argtypes = [I32, I32, P, P, F64, F64]
-        lib.orc_literal_decrease.restype = I32
-        _lib = lib
+        _lib = _declare(ctypes.CDLL(_LIB))
     return _lib
+
+
+def _declare(lib):
+    """Argument and result types of the oracle's entry points."""
+    P, I32, I64, F64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.orc_parallel_l0.argtypes = [I64, I32, I32, P, P, F64, I32, I32, F64, I32, P, P, P, P, P, P, P,
+                                    P]
+    lib.orc_parallel_l0.restype = ctypes.c_int
+    lib.orc_serial_l0.argtypes = [I64, I32, I32, P, P, F64, I32, I32, F64, P, P, P, P, P]
+    lib.orc_serial_l0.restype = ctypes.c_int
+    lib.orc_residual.argtypes = [I64, I32, I32, P, P, P, P, P]
+    lib.orc_residual.restype = None
+    lib.orc_score_columns.argtypes = [I64, I32, P, P, F64, I32, I32, P, P, P]
+    lib.orc_score_columns.restype = None
+    lib.orc_score_columns_shifted.argtypes = [I64, I32, P, P, F64, I32, I32, I32, P, P]
+    lib.orc_score_columns_shifted.restype = None
+    lib.orc_literal_decrease.argtypes = [I32, I32, P, P, F64, F64]
+    lib.orc_literal_decrease.restype = I32
+    return lib
 
 
 def _p(a):
@@ -72,11 +92,14 @@ def _c(a, dt):
 
 
 def parallel_l0(n, m, d, col_idx, y, alpha, *, max_iter=100, tol=1e-10, rule=RULE_L0DEC,
-                x_init=None, w=None):
+                x_init=None, w=None, tol_mode=TOL_RELATIVE, threads=False):
     """Run Parallel-l0 (rules L0DEC, MODE) or its shifted form (Algorithm 3;
     rules SHIFTED_L0DEC, SHIFTED_MODE), on a column-scaled A when column
     weights w are given (Section 4.3.3); returns dict(x, iters, outcome,
-    trace, tsize, passes) where passes counts vote passes."""
+    trace, tsize, passes) where passes counts vote passes.  ValueError on
+    invalid input, including a column that lists a row twice (A is binary
+    with d ones per column, Definition 2.2).  threads=True runs the OpenMP
+    build on all host cores (OMP_NUM_THREADS), bitwise the same result."""
     col_idx, y = _c(col_idx, np.int32), _c(y, np.float64)
     xi = None if x_init is None else _c(x_init, np.float64)
     wv = None if w is None else _c(w, np.float64)
@@ -86,8 +109,8 @@ def parallel_l0(n, m, d, col_idx, y, alpha, *, max_iter=100, tol=1e-10, rule=RUL
     trace = np.zeros(max_iter + 1, dtype=np.int32)
     tsize = np.zeros(max(max_iter, 1), dtype=np.int64)
     iters, outcome, passes = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    rc = _load().orc_parallel_l0(n, m, d, _p(col_idx), _p(y), float(alpha), rule, max_iter,
-                                 float(tol), _p(xi), _p(wv), _p(x), _p(trace), _p(tsize),
+    rc = _load(threads).orc_parallel_l0(n, m, d, _p(col_idx), _p(y), float(alpha), rule, max_iter,
+                                 float(tol), int(tol_mode), _p(xi), _p(wv), _p(x), _p(trace), _p(tsize),
                                  ctypes.byref(iters), ctypes.byref(outcome), ctypes.byref(passes))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")

@@ -1,17 +1,26 @@
 /*
  * ORACLE — TEST INFRASTRUCTURE ONLY.
  *
- * A plain, slow, single-threaded FP64 implementation of Serial-l0 and
+ * A plain, slow FP64 implementation of Serial-l0 and
  * Parallel-l0 (Mendoza-Smith & Tanner, "Expander l0-decoding", Algorithms 1
- * and 2, selection rule eq. (selection_l0) in Section 3).  Only the test
+ * and 2, selection rule eq. (selection_l0) in Section 4).  Only the test
  * suite, the package's smoke check and the benchmark's CPU-baseline leg call
  * it; the GPU decoder shares no code with it.  Built with -O2
  * -ffp-contract=off and no fast-math, so every sum, difference and
  * comparison below is one IEEE-754 binary64 operation in the order written.
+ * The plain build is single-threaded; a second build of this same file with
+ * OpenMP splits the Parallel-l0 vote's columns over threads (nothing else),
+ * which changes no arithmetic: both builds give the same result bit for bit.
+ *
+ * Input (Definition 2.2): A is the binary adjacency matrix of a left
+ * d-regular bipartite graph, so column j has exactly d ones, at d distinct
+ * rows.  A column that lists a row twice is not such a matrix and the run is
+ * rejected as invalid input, like a row index outside [0, m).
  *
  * Readings of the paper that this file fixes (the paper leaves them open):
- *  - zero test and equality: with tau = tol * max_i |y_i|, an entry v counts
- *    as nonzero iff |v| > tau; the paper's exact equality is tol = 0;
+ *  - zero test and equality: with tau = tol * max_i |y_i| (or tau = tol in
+ *    the absolute mode), an entry v counts as nonzero iff |v| > tau; the
+ *    paper's exact equality is tol = 0;
  *  - candidate values: for column j only the nonzero values of r on N(j) are
  *    tried as omega (any other omega leaves every entry of r_N(j) nonzero
  *    when tau = 0, so it cannot decrease ||r||_0);
@@ -60,6 +69,7 @@
 
 enum { ORC_RULE_L0DEC = 0, ORC_RULE_MODE = 1, ORC_RULE_SHIFTED_L0DEC = 2, ORC_RULE_SHIFTED_MODE = 3 };
 enum { ORC_CONVERGED = 0, ORC_STALLED = 1, ORC_MAX_ITER = 2 };
+enum { ORC_TOL_RELATIVE = 0, ORC_TOL_ABSOLUTE = 1 };
 
 static int is_nonzero(double v, double tau) { return fabs(v) > tau; }
 
@@ -124,20 +134,33 @@ static int weights_ok(int64_t n, const double* w) {
     return 1;
 }
 
+/* Column j of A: d row indices, each in [0, m), no row twice (Definition
+ * 2.2: a binary matrix with exactly d ones per column). */
+static int column_ok(int32_t m, int32_t d, const int32_t* rows) {
+    for (int32_t t = 0; t < d; ++t) {
+        if (rows[t] < 0 || rows[t] >= m) return 0;
+        for (int32_t u = 0; u < t; ++u)
+            if (rows[u] == rows[t]) return 0;
+    }
+    return 1;
+}
+
 static int args_ok(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const double* y,
                    double alpha, int32_t rule, int32_t max_iter, double tol) {
     if (n < 1 || m < 1 || d < 2 || d > m || !col_idx || !y) return 0;
     if (!(alpha > 1.0) || !(alpha <= (double)d)) return 0;
     if (rule < ORC_RULE_L0DEC || rule > ORC_RULE_SHIFTED_MODE) return 0;
     if (max_iter < 0 || !(tol >= 0.0) || !isfinite(tol)) return 0;
-    for (int64_t e = 0; e < n * (int64_t)d; ++e)
-        if (col_idx[e] < 0 || col_idx[e] >= m) return 0;
+    for (int64_t j = 0; j < n; ++j)
+        if (!column_ok(m, d, col_idx + j * d)) return 0;
     for (int32_t i = 0; i < m; ++i)
         if (!isfinite(y[i])) return 0;
     return 1;
 }
 
-static double zero_threshold(int32_t m, const double* y, double tol) {
+/* tau = tol * max_i |y_i| (relative, tol_mode 0) or tau = tol (absolute). */
+static double zero_threshold(int32_t m, const double* y, double tol, int32_t tol_mode) {
+    if (tol_mode == ORC_TOL_ABSOLUTE) return tol;
     double s = 0.0;
     for (int32_t i = 0; i < m; ++i)
         if (fabs(y[i]) > s) s = fabs(y[i]);
@@ -205,7 +228,8 @@ int32_t orc_literal_decrease(int32_t m, int32_t d, const int32_t* rows, const do
 }
 
 /*
- * Parallel-l0 (Algorithm 2).  x_init (optional) resumes from a previous
+ * Parallel-l0 (Algorithm 2).  tol_mode 0 takes tau = tol * max_i |y_i|, 1
+ * takes tau = tol.  x_init (optional) resumes from a previous
  * estimate; w (optional) gives the column weights of a column-scaled A;
  * x_out[n] receives x_hat.  trace[0..iters] receives ||r||_0 after
  * each residual update (trace[0] for the start), tsize[0..iters) the number
@@ -213,16 +237,16 @@ int32_t orc_literal_decrease(int32_t m, int32_t d, const int32_t* rows, const do
  * slots.  Returns 0, or -1 on invalid arguments.
  */
 int orc_parallel_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const double* y,
-                    double alpha, int32_t rule, int32_t max_iter, double tol, const double* x_init,
+                    double alpha, int32_t rule, int32_t max_iter, double tol, int32_t tol_mode,
+                    const double* x_init,
                     const double* w, double* x_out, int32_t* trace, int64_t* tsize, int32_t* iters,
                     int32_t* outcome, int32_t* passes) {
     if (!args_ok(n, m, d, col_idx, y, alpha, rule, max_iter, tol) || !weights_ok(n, w) || !x_out ||
-        !trace || !iters || !outcome)
+        !trace || !iters || !outcome || (tol_mode != ORC_TOL_RELATIVE && tol_mode != ORC_TOL_ABSOLUTE))
         return -1;
     const int32_t a = (int32_t)ceil(alpha);
-    const double tau = zero_threshold(m, y, tol);
+    const double tau = zero_threshold(m, y, tol, tol_mode);
     double* r = (double*)malloc(sizeof(double) * (size_t)m);
-    double* v = (double*)malloc(sizeof(double) * (size_t)d);
     double* omega = (double*)malloc(sizeof(double) * (size_t)n);
     uint8_t* sel = (uint8_t*)malloc((size_t)n);
 
@@ -234,16 +258,25 @@ int orc_parallel_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, con
     for (;;) {
         if (trace[l] == 0) { *outcome = ORC_CONVERGED; break; }
         if (l == max_iter) { *outcome = ORC_MAX_ITER; break; }
-        /* every column is scored on the same residual */
+        /* every column is scored on the same residual; no column's score
+           depends on another's, so a build with OpenMP may split the columns
+           over threads (each with a gather buffer of its own) and gets the
+           same selections bit for bit */
         int64_t chosen = 0;
-        for (int64_t j = 0; j < n; ++j) {
-            int32_t best;
-            for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d + t]];
-            if (shifted)
-                sel[j] = (uint8_t)score_column_shifted(d, v, p % d, tau, rule, a, &omega[j]);
-            else
-                sel[j] = (uint8_t)score_column(d, v, tau, rule, a, &omega[j], &best);
-            chosen += sel[j];
+#pragma omp parallel reduction(+ : chosen)
+        {
+            double* vt = (double*)malloc(sizeof(double) * (size_t)d);
+#pragma omp for schedule(static)
+            for (int64_t j = 0; j < n; ++j) {
+                int32_t best;
+                for (int32_t t = 0; t < d; ++t) vt[t] = r[col_idx[j * d + t]];
+                if (shifted)
+                    sel[j] = (uint8_t)score_column_shifted(d, vt, p % d, tau, rule, a, &omega[j]);
+                else
+                    sel[j] = (uint8_t)score_column(d, vt, tau, rule, a, &omega[j], &best);
+                chosen += sel[j];
+            }
+            free(vt);
         }
         ++p;
         if (chosen == 0) {
@@ -264,7 +297,7 @@ int orc_parallel_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, con
     }
     *iters = l;
     if (passes) *passes = p;
-    free(r); free(v); free(omega); free(sel);
+    free(r); free(omega); free(sel);
     return 0;
 }
 
@@ -285,7 +318,7 @@ int orc_serial_l0(int64_t n, int32_t m, int32_t d, const int32_t* col_idx, const
         !sweeps || !outcome || rule > ORC_RULE_MODE)
         return -1;
     const int32_t a = (int32_t)ceil(alpha);
-    const double tau = zero_threshold(m, y, tol);
+    const double tau = zero_threshold(m, y, tol, ORC_TOL_RELATIVE);
     /* rows of A as ascending column lists (a counting sort over columns) */
     int64_t* rowptr = (int64_t*)calloc((size_t)m + 1, sizeof(int64_t));
     int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)m);

@@ -258,7 +258,7 @@ def test_serial_and_parallel_agree():
 
 
 def test_mode_rule_false_updates_grow_residual():
-    """Section 3.5.2: zeros in r_N(j) matter.  On W1 the frequency score adds
+    """Section 3.5.3 (the mode does not minimise ||r||_0): zeros in r_N(j) matter.  On W1 the frequency score adds
     wrong values and raises ||r||_0 where the l0-decrease does not."""
     fx = load("W1.json")
     n, m, d, col = graph_arrays(fx["graph"])
@@ -324,3 +324,57 @@ def test_argument_checks():
         oracle.parallel_l0(inst.n, inst.m, inst.d, bad, inst.y, 2)
     with pytest.raises(ValueError):
         oracle.parallel_l0(inst.n, inst.m, inst.d, inst.col_idx, inst.y, 2, tol=-1.0)
+
+
+# --------------------------------------------------------------------------
+# input of the decoders: A is binary with d distinct rows per column
+# --------------------------------------------------------------------------
+
+def test_repeated_row_in_a_column_is_rejected():
+    """Definition 2.2: A is the binary adjacency matrix of a left d-regular
+    graph, exactly d ones per column, so a column listing one row twice is no
+    such matrix.  The case of rows (0, 0, 1) with r = (2, 5) shows why it
+    cannot be decoded as if it were one: counted as two unit entries, omega = 2
+    zeroes both copies (decrease 2 >= alpha = 2 at tau = 0); read as an entry
+    A_00 = 2, the decrease of omega = 2 is 0.  The oracle refuses it, both
+    decoders, whatever position the copy is in."""
+    y = np.array([2.0, 5.0, 0.0, 0.0])
+    good = np.array([0, 2, 1, 1, 2, 3], dtype=np.int32)
+    oracle.parallel_l0(2, 4, 3, good, y, 2, tol=0.0)   # a valid graph runs
+    oracle.serial_l0(2, 4, 3, good, y, 2, tol=0.0)
+    for bad in ([0, 0, 1, 1, 2, 3], [0, 1, 0, 1, 2, 3], [0, 2, 1, 3, 2, 3], [0, 2, 1, 1, 3, 3]):
+        col = np.array(bad, dtype=np.int32)
+        with pytest.raises(ValueError):
+            oracle.parallel_l0(2, 4, 3, col, y, 2, tol=0.0)
+        with pytest.raises(ValueError):
+            oracle.serial_l0(2, 4, 3, col, y, 2, tol=0.0)
+    # the last column of a generated instance, and every rule
+    inst = gen.make_instance(2, 300, 40, 5, 4)
+    col = inst.col_idx.copy()
+    col[-1] = col[-3]
+    for rule in RULES.values():
+        with pytest.raises(ValueError):
+            oracle.parallel_l0(inst.n, inst.m, inst.d, col, inst.y, 2, rule=rule)
+
+
+def test_absolute_tolerance_is_tau_itself():
+    """In the absolute mode tau = tol: a run at tol = fl(t * max|y|) makes
+    the same zero/equality decisions as the relative run at t (the same
+    double tau), bit for bit; and tol >= max|y| makes every entry of y zero,
+    so the run converges at once with x_hat = 0."""
+    inst = gen.make_instance(5, 20000, 2000, 7, 120)
+    s = float(np.max(np.abs(inst.y)))
+    for t in (1e-10, 1e-3, 0.0):
+        rel = oracle.parallel_l0(inst.n, inst.m, inst.d, inst.col_idx, inst.y, 4, tol=t)
+        ab = oracle.parallel_l0(inst.n, inst.m, inst.d, inst.col_idx, inst.y, 4, tol=t * s,
+                                tol_mode=oracle.TOL_ABSOLUTE)
+        assert ab["outcome"] == rel["outcome"] and ab["trace"].tolist() == rel["trace"].tolist()
+        assert np.array_equal(ab["x"].view(np.int64), rel["x"].view(np.int64))
+    top = oracle.parallel_l0(inst.n, inst.m, inst.d, inst.col_idx, inst.y, 4, tol=s,
+                             tol_mode=oracle.TOL_ABSOLUTE)
+    assert top["outcome"] == oracle.CONVERGED and top["iters"] == 0 and top["trace"].tolist() == [0]
+    assert not np.any(top["x"])
+    # just below max|y|: the largest entry stays nonzero
+    below = oracle.parallel_l0(inst.n, inst.m, inst.d, inst.col_idx, inst.y, 4,
+                               tol=np.nextafter(s, 0.0), tol_mode=oracle.TOL_ABSOLUTE)
+    assert below["trace"][0] == int(np.sum(np.abs(inst.y) == s))

@@ -26,19 +26,22 @@ MUTANTS = {
     "drop_zero_count": ("(rule == ORC_RULE_MODE) ? freq : before - after;", "(rule == ORC_RULE_MODE) ? freq : d - after;"),
     "shift_drop_zero_count": ("(shifted_rule == ORC_RULE_SHIFTED_MODE) ? freq : before - after;",
                               "(shifted_rule == ORC_RULE_SHIFTED_MODE) ? freq : d - after;"),
-    "threshold_floor": ("const int32_t a = (int32_t)ceil(alpha);\n    const double tau = zero_threshold(m, y, tol);\n    double* r",
-                        "const int32_t a = (int32_t)floor(alpha);\n    const double tau = zero_threshold(m, y, tol);\n    double* r"),
+    "threshold_floor": ("const int32_t a = (int32_t)ceil(alpha);\n    const double tau = zero_threshold(m, y, tol, tol_mode);",
+                        "const int32_t a = (int32_t)floor(alpha);\n    const double tau = zero_threshold(m, y, tol, tol_mode);"),
     "strict_threshold": ("return top != INT_MIN && top >= a;", "return top != INT_MIN && top > a;"),
     "zero_test_nonstrict": ("return fabs(v) > tau;", "return fabs(v) >= tau;"),
-    "gather_index": ("for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d + t]];\n            if (shifted)",
-                     "for (int32_t t = 0; t < d; ++t) v[t] = r[col_idx[j * d]];\n            if (shifted)"),
+    "gather_index": ("for (int32_t t = 0; t < d; ++t) vt[t] = r[col_idx[j * d + t]];",
+                     "for (int32_t t = 0; t < d; ++t) vt[t] = r[col_idx[j * d]];"),
     "residual_skips_last_row": ("for (int32_t i = 0; i < m; ++i) r[i] = y[i] - s[i];",
                                 "for (int32_t i = 0; i + 1 < m; ++i) r[i] = y[i] - s[i];"),
     "serial_row_recompute_missing": ("r[i] = y[i] - s;", "r[i] = y[i] - s * (t == 0);"),
     "tau_absolute": ("return tol * s;", "return tol;"),
-    "shift_offset": ("score_column_shifted(d, v, p % d,", "score_column_shifted(d, v, (p + 1) % d,"),
-    "shift_position_by_update": ("score_column_shifted(d, v, p % d,", "score_column_shifted(d, v, l % d,"),
+    "shift_offset": ("score_column_shifted(d, vt, p % d,", "score_column_shifted(d, vt, (p + 1) % d,"),
+    "shift_position_by_update": ("score_column_shifted(d, vt, p % d,", "score_column_shifted(d, vt, l % d,"),
     "shift_no_retry": ("if (shifted && ++empty < d) continue;", "if (shifted && ++empty < 1) continue;"),
+    "repeated_row_accepted": ("if (rows[u] == rows[t]) return 0;", "if (rows[u] == rows[t] && m < 0) return 0;"),
+    "repeated_row_first_only": ("for (int32_t u = 0; u < t; ++u)", "for (int32_t u = 0; u < t && u < 1; ++u)"),
+    "absolute_mode_ignored": ("    if (tol_mode == ORC_TOL_ABSOLUTE) return tol;\n", ""),
     "shift_zero_candidate": ("    *omega = 0.0;\n    if (!is_nonzero(v[t], tau)) return 0;\n", "    *omega = 0.0;\n"),
 }
 
@@ -68,11 +71,13 @@ def _run_pins():
         ("scaled_literal", lambda: cpins.test_scaled_selection_is_the_literal_decrease(oracle.RULE_L0DEC)),
         ("scaled_residual", cpins.test_scaled_residual_against_a_dense_product),
         ("scaled_pm1", lambda: cpins.test_pm1_signals_recovered_only_with_scaled_columns(0)),
+        ("repeated_row", pins.test_repeated_row_in_a_column_is_rejected),
+        ("absolute_tau", pins.test_absolute_tolerance_is_tau_itself),
     ]
     for name, fn in checks:
         try:
             fn()
-        except (AssertionError, ValueError):
+        except (AssertionError, ValueError, pytest.fail.Exception):
             failed.append(name)
     return failed
 
