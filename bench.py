@@ -36,8 +36,63 @@ sys.path.insert(0, ROOT)
 METRIC = "Parallel-ℓ0 solve time & HBM GB/s at n=2^24; batched solves/sec vs plain"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1508_01256_amd/csrc/l0_kernels.hip", "paper_1508_01256_amd/csrc/l0_internal.h",
-                  "paper_1508_01256_amd/csrc/l0_filter.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_kernel_n2^24_traffic.json")
+                  "paper_1508_01256_amd/csrc/l0_filter.h", "paper_1508_01256_amd/csrc/l0_common.h"]
+SIZES = ("n2^24", "n2^20")
+
+
+def traffic_file(size: str) -> str:
+    return os.path.join(ROOT, "profiles", f"solve_kernel_{size}_traffic.json")
+
+
+def host_cpu():
+    """(logical CPUs this process may use, CPU model name)."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, model
+
+
+def oracle_threads():
+    """Threads the OpenMP oracle build uses: OMP_NUM_THREADS when set, else
+    every CPU this process may use."""
+    cores, _ = host_cpu()
+    try:
+        return max(1, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    except ValueError:
+        return cores
+
+
+def oracle_pool_check(insts, results, xs, rule=0, alpha=None):
+    """Run the single-threaded oracle on every instance (a thread pool over
+    the instances: the oracle releases the GIL while it runs) and compare with
+    the GPU's results: outcome, iterations and x_hat bitwise.  Returns
+    (agree, checked, seconds, threads)."""
+    import numpy as np
+
+    import oracle
+    threads = oracle_threads()
+
+    def one(q):
+        i = insts[q]
+        o = oracle.parallel_l0(i.n, i.m, i.d, i.col_idx, i.y, i.alpha if alpha is None else alpha,
+                               max_iter=100, tol=1e-10, rule=rule, w=i.w)
+        r = results[q]
+        return int(o["outcome"] == r["outcome"] and o["iters"] == r["iters"] and np.array_equal(o["x"], xs[q]))
+
+    c0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as pool:
+        agree = sum(pool.map(one, range(len(insts))))
+    return agree, len(insts), time.perf_counter() - c0, threads
 
 
 def kernel_hash() -> str:
@@ -48,11 +103,11 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(size="n2^24"):
     """HBM bytes per solve launch from the committed rocprofv3 counter runs,
     or None when the kernel source changed since they were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(size)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -93,6 +148,10 @@ def main():
     ap.add_argument("--repeats", type=int, default=30, help="l0_solve launches timed for the roofline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--kind", choices=["normal", "pm1"], default="normal")
+    ap.add_argument("--size", choices=SIZES, default="n2^24",
+                    help="single: n=2^24, m=16777 (default) or n=2^20, m=104858")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="single: skip the batched-sweep leg reported in the line's detail")
     ap.add_argument("--workload", choices=["single", "sweep", "serve", "phase"], default="single",
                     help="single: one n=2^24 instance (default); sweep: 4096 phase-transition "
                          "instances through the batched decoder; serve: 2000 Poisson-arriving "
@@ -142,7 +201,7 @@ def main():
         return phase(args)
     kind = gen.VALUES_NORMAL if args.kind == "normal" else gen.VALUES_PM1
     t0 = time.time()
-    inst = gen.single_workload("n2^24", 0, kind=kind)
+    inst = gen.single_workload(args.size, 0, kind=kind)
     n, m, d, alpha, max_iter, tol = inst.n, inst.m, inst.d, inst.alpha, 100, 1e-10
     print(f"[bench] generated n={n} m={m} d={d} k={inst.k} in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
@@ -234,25 +293,41 @@ def main():
           f"prep {prep_ms:.2f} ms", file=sys.stderr, flush=True)
     A.close()
 
-    traffic = measured_traffic()
+    traffic = measured_traffic(args.size)
+    kname = f"l0::solve_kernel<{d},{'true' if index_bytes(m) == 2 else 'false'}>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "l0::solve_kernel<7,true>", "bytes_per_launch": bytes_launch,
+                "kernel": kname, "bytes_per_launch": bytes_launch,
                 "avg_launch_ms": round(solve_avg, 4), "stored_bytes_per_launch": stored_launch,
                 "stored_gbs": round(stored_gbs, 1)}
+    if traffic:
+        # the bytes the counters saw per launch, over the same launch time
+        roofline["counter_gbs"] = round(traffic / (solve_avg * 1e-3) / 1e9, 1)
+        roofline["counter_frac"] = round(traffic / (solve_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    gx = xs.cpu().numpy()
+    del xs, rs, x, res, ws, trace, tsize, tl
 
     cpu = None
     if not args.no_cpu:
         import oracle
+        cores, model = host_cpu()
         c0 = time.perf_counter()
-        o = oracle.parallel_l0(n, m, d, inst.col_idx, inst.y, alpha, max_iter=max_iter, tol=tol)
-        cdt = time.perf_counter() - c0
-        ok = (o["iters"] == iters and np.array_equal(o["x"], xs.cpu().numpy()))
-        cpu = {"value": round(1.0 / cdt, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": f"1 full decode of the same n=2^24 instance ({cdt:.1f} s, single thread, "
-                         f"gcc -O2; parity with GPU: {'bitwise' if ok else 'MISMATCH'})"}
-        print(f"[bench] oracle {cdt:.2f} s/solve, parity {'ok' if ok else 'MISMATCH'}",
-              file=sys.stderr, flush=True)
+        o1 = oracle.parallel_l0(n, m, d, inst.col_idx, inst.y, alpha, max_iter=max_iter, tol=tol)
+        t1 = time.perf_counter() - c0
+        threads = oracle_threads()
+        c0 = time.perf_counter()
+        on = oracle.parallel_l0(n, m, d, inst.col_idx, inst.y, alpha, max_iter=max_iter, tol=tol, threads=True)
+        tn = time.perf_counter() - c0
+        ok1 = o1["iters"] == iters and np.array_equal(o1["x"], gx)
+        okn = on["iters"] == iters and np.array_equal(on["x"], gx)
+        cpu = {"value": round(1.0 / tn, 5), "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "sample": f"1 full decode of the same {args.size} instance with the oracle's OpenMP build "
+                         f"({tn:.2f} s on {threads} threads of {cores} CPUs, {model}); the plain "
+                         f"single-threaded build {t1:.2f} s ({1.0 / t1:.4f} solves/s); gcc -O2; parity "
+                         f"with GPU: {'bitwise' if ok1 and okn else 'MISMATCH'}",
+               "single_thread_value": round(1.0 / t1, 5)}
+        print(f"[bench] oracle {t1:.2f} s/solve on 1 thread, {tn:.2f} s on {threads}, parity "
+              f"{'ok' if ok1 and okn else 'MISMATCH'}", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -267,7 +342,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"Parallel-l0 single instance n=2^24 m={m} d={d} k={inst.k} "
+        "config": {"workload": f"Parallel-l0 single instance n={args.size[1:]} m={m} d={d} k={inst.k} "
                                f"alpha={alpha:g} tol={tol:g} max_iter={max_iter} "
                                f"{'N(0,1)' if kind == 0 else 'uniform +-1'} nonzeros, seed {inst.seed}",
                    "n": n, "m": m, "d": d, "k": inst.k, "alpha": alpha, "step": "l0_decode_ex (repack + solve)"},
@@ -281,7 +356,25 @@ def main():
                    "solves_per_s_prepared": round(1e3 / solve_avg, 3),
                    "phase_us": phases_us, "startup_us": startup_us},
     }
+    if not args.no_sweep:
+        # the metric's second half: the batched decoder against the plain
+        # one-launch-per-instance loop on the 4096-instance sweep
+        out["detail"]["batched_sweep"] = run_sweep(args.sweep_count, steps=5, warmup=1,
+                                                   check=not args.no_cpu)["summary"]
     print(json.dumps(out), flush=True)
+
+
+def release_device():
+    """Free what torch's caching allocator holds before the interpreter
+    exits (nothing of the device is left for static destructors to free)."""
+    import gc
+
+    import torch
+    if not torch.cuda.is_initialized():
+        return
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
 
 def solve_bytes(n, m, d, iters, outcome, tsizes):
@@ -291,16 +384,18 @@ def solve_bytes(n, m, d, iters, outcome, tsizes):
     return 8 * n + passes * (4 * n * d + 16 * m) + sum((16 + 4 * d) * t for t in tsizes)
 
 
-def sweep(args):
-    """Batched phase-transition sweep: all instances in one l0_decode_batched
-    call per step, against a plain loop of one l0_decode_ex per instance."""
+def run_sweep(count, steps, warmup, check=True, autotune=False, schedule=(512, 32768)):
+    """The batched phase-transition sweep: all instances in one
+    l0_decode_batched call per step (timed over `steps`), against a plain
+    loop of one l0_decode_ex per instance on one stream; per-(delta, rho)
+    cell success; with `check`, every instance against the oracle.  Returns
+    dict(summary=..., ms_per_step, bytes_total, schedule, cpu)."""
     import numpy as np
     import torch
 
     import gen
     import paper_1508_01256_amd as l0
 
-    count = args.sweep_count
     params = gen.sweep_params(4096)[:count]
     t0 = time.time()
     insts = [gen.make_instance(p["seed"], p["n"], p["m"], p["d"], p["k"]) for p in params]
@@ -312,9 +407,9 @@ def sweep(args):
     print(f"[bench] generated and uploaded {count} sweep instances in {time.time() - t0:.1f}s "
           f"(index bytes {sum(4 * i.n * i.d for i in insts) / 1e9:.2f} GB)", file=sys.stderr, flush=True)
     table = l0.problem_table(probs)
-    opts = l0.l0_batch_opts(0, 0, 512, 32768)
+    opts = l0.l0_batch_opts(0, 0, *schedule)
     results = l0.new_results(count, dev)
-    if args.autotune:
+    if autotune:
         ws = torch.empty(l0.l0_batch_workspace_bytes(table, None), dtype=torch.uint8, device=dev)
         st = l0.l0_batch_autotune(table, opts, results, ws)
         assert st == l0.L0_OK, st
@@ -329,16 +424,16 @@ def sweep(args):
         if st != l0.L0_OK:
             raise RuntimeError(f"l0_decode_batched status {st}")
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     e1.record(stream)
     torch.cuda.synchronize()
-    ms_per_step = e0.elapsed_time(e1) / args.steps
+    ms_per_step = e0.elapsed_time(e1) / steps
     rl = l0.results_list(results)
     xs = [p["x_out"].cpu().numpy() for p in probs]
 
@@ -367,6 +462,7 @@ def sweep(args):
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - p0
     same = all(torch.equal(a, b["x_out"]) for a, b in zip(xp, probs))
+    del xp, ws1, ws, probs, tim
 
     # success (||x_hat - x||_inf <= 1e-12 ||x||_inf; k = 0: x_hat = 0) per (delta, rho-bin) cell
     def success(i, x):
@@ -382,23 +478,21 @@ def sweep(args):
         a, b = cells.get(key, (0, 0))
         cells[key] = (a + int(ok), b + 1)
 
-    bytes_total = 0
     cpu = None
-    sample = list(range(0, count, 16))
-    import oracle
-    c0 = time.perf_counter()
-    agree = 0
-    for q in sample:
-        i = insts[q]
-        o = oracle.parallel_l0(i.n, i.m, i.d, i.col_idx, i.y, i.alpha, max_iter=100, tol=1e-10)
-        agree += int(o["iters"] == rl[q]["iters"] and np.array_equal(o["x"], xs[q]))
-    cdt = time.perf_counter() - c0
-    if not args.no_cpu:
-        cpu = {"value": round(len(sample) / cdt, 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(sample)} instances (every 16th of the sweep), {cdt:.1f} s single thread; "
-                         f"{agree}/{len(sample)} bitwise equal to the batched GPU results"}
+    agree = checked = None
+    if check:
+        # every instance through the oracle: the per-cell success counts are
+        # then the oracle's too (an instance agrees only if outcome,
+        # iterations and x_hat are bitwise equal)
+        agree, checked, cdt, threads = oracle_pool_check(insts, rl, xs)
+        cores, model = host_cpu()
+        cpu = {"value": round(checked / cdt, 3), "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "sample": f"all {checked} instances, single-threaded oracle on a pool of {threads} threads "
+                         f"({cores} CPUs, {model}), {cdt:.1f} s; {agree}/{checked} bitwise equal to the "
+                         "batched GPU results"}
     # algorithmic bytes: per instance, vote passes from the outcome; the |T| term is linear, so
     # the total update count gives it exactly
+    bytes_total = 0
     for i, r in zip(insts, rl):
         it, oc = r["iters"], r["outcome"]
         bytes_total += solve_bytes(i.n, i.m, i.d, it, oc, [r["updates"]] if it else [])
@@ -406,34 +500,49 @@ def sweep(args):
     print(f"[bench] batched {ms_per_step:.2f} ms per sweep ({count / ms_per_step * 1e3:.0f} solves/s); "
           f"plain loop {plain_s * 1e3:.1f} ms ({count / plain_s:.0f} solves/s), same x: {same}; "
           f"span {span_us / 1e3:.2f} ms, workgroup-busy {busy / 1e3:.0f} ms, phases {phase_ms}; "
-          f"oracle agreement {agree}/{len(sample)}", file=sys.stderr, flush=True)
+          f"oracle agreement {agree}/{checked}", file=sys.stderr, flush=True)
     for key in sorted(cells):
         a, b = cells[key]
         print(f"[bench]   {key}: {a}/{b} recovered", file=sys.stderr)
+    summary = {"instances": count, "ms_per_sweep": round(ms_per_step, 3),
+               "solves_per_s": round(count / ms_per_step * 1e3, 1),
+               "plain_loop_solves_per_s": round(count / plain_s, 1),
+               "speedup_vs_plain": round(plain_s * 1e3 / ms_per_step, 2),
+               "plain_results_identical": same, "gbs_method_bytes": round(achieved, 1),
+               "frac": round(achieved / HBM_PEAK_GBS, 4),
+               "schedule": {"block_threads": opts.block_threads, "words_cap": opts.words_cap},
+               "oracle_agree": agree, "oracle_checked": checked, "recovered": int(sum(succ))}
+    return dict(summary=summary, ms_per_step=ms_per_step, bytes_total=bytes_total, achieved=achieved,
+                cpu=cpu, cells=cells, span_ms=span_us / 1e3, busy_ms=busy / 1e3, phase_ms=phase_ms,
+                outcomes={l0.OUTCOME_NAMES[k]: int(sum(r["outcome"] == k for r in rl)) for k in (0, 1, 2)})
+
+
+def sweep(args):
+    """The batched phase-transition sweep as a bench line of its own."""
+    count = args.sweep_count
+    r = run_sweep(count, args.steps, args.warmup, check=not args.no_cpu, autotune=args.autotune)
+    sm = r["summary"]
     out = {
         "metric": "batched Parallel-l0 solves/s on the phase-transition sweep vs a plain loop",
-        "value": round(count / ms_per_step * 1e3, 1),
+        "value": sm["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": sm["ms_per_sweep"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{count} instances, n=round(2^U) U~U[10,18], delta in "
                                "{0.01,0.03,0.1,0.3}, d in {5,7,9}, rho~U[0.05,0.5], alpha=ceil(d/2), "
                                "max_iter=100, tol=1e-10, N(0,1) nonzeros",
-                   "schedule": {"block_threads": opts.block_threads, "words_cap": opts.words_cap}},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                   "schedule": sm["schedule"]},
+        "roofline": {"bound": "hbm", "achieved": round(r["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(r["achieved"] / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "l0::batch_kernel (all launches of one sweep)",
-                     "bytes_per_launch": bytes_total},
-        "cpu_baseline": cpu,
-        "detail": {"plain_loop_solves_per_s": round(count / plain_s, 1),
-                   "speedup_vs_plain": round(plain_s * 1e3 / ms_per_step, 2),
-                   "plain_results_identical": same, "span_ms": round(span_us / 1e3, 3),
-                   "workgroup_busy_ms": round(busy / 1e3, 1), "phase_ms": phase_ms,
-                   "recovered": int(sum(succ)),
-                   "outcomes": {l0.OUTCOME_NAMES[k]: int(sum(r["outcome"] == k for r in rl)) for k in (0, 1, 2)},
-                   "cells": {k: f"{a}/{b}" for k, (a, b) in sorted(cells.items())}},
+                     "bytes_per_launch": r["bytes_total"]},
+        "cpu_baseline": r["cpu"],
+        "detail": {**{k: v for k, v in sm.items() if k not in ("schedule",)},
+                   "span_ms": round(r["span_ms"], 3), "workgroup_busy_ms": round(r["busy_ms"], 1),
+                   "phase_ms": r["phase_ms"], "outcomes": r["outcomes"],
+                   "cells": {k: f"{a}/{b}" for k, (a, b) in sorted(r["cells"].items())}},
     }
     print(json.dumps(out), flush=True)
 
@@ -823,3 +932,6 @@ def phase(args):
 
 if __name__ == "__main__":
     main()
+    # every tensor of the run is gone with main's frame: hand the cached
+    # device memory back while the runtime is fully up
+    release_device()

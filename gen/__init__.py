@@ -79,6 +79,16 @@ def columns(seed: int, n: int, m: int, d: int) -> np.ndarray:
     return out
 
 
+def permute_rows(col_idx: np.ndarray, d: int, seed: int) -> np.ndarray:
+    """A copy of col_idx with each column's d rows in a seeded random order
+    (the same graph A; only the order in which a column lists its rows
+    changes)."""
+    col = np.ascontiguousarray(col_idx, dtype=np.int32).reshape(-1, d)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    order = np.argsort(rng.random(col.shape), axis=1, kind="stable")
+    return np.take_along_axis(col, order, axis=1).reshape(-1).copy()
+
+
 def support(seed: int, n: int, k: int) -> np.ndarray:
     """int64[k]: a uniform k-subset of [0, n), ascending."""
     out = np.empty(k, dtype=np.int64)

@@ -10,12 +10,16 @@
  *     x_hat_j <- x_hat_j + omega for (j, omega) in T
  *     r <- y - A x_hat
  * where every column j is scored on the same residual r (eq. (selection_l0),
- * Section 3).
+ * Section 4).
  *
  * Conventions shared by every entry point:
  *  - A is passed as col_idx: int32[n*d], column j's d row indices at
- *    col_idx[j*d .. j*d+d), each in [0, m).  Row order inside a column does
- *    not matter.
+ *    col_idx[j*d .. j*d+d), each in [0, m), d distinct rows per column (A is
+ *    binary with exactly d ones per column, Definition 2.2).  An index outside
+ *    [0, m) ends the solve with L0_DEV_BAD_INDEX, a row listed twice in one
+ *    column with L0_DEV_REPEATED_ROW.  Row order inside a column does not
+ *    change the result of L0_RULE_L0DEC or L0_RULE_MODE; the shifted rules
+ *    try the rows in col_idx order, so for them it does.
  *  - Zero test and equality use tau = tol * max_i |y_i| (or tau = tol with
  *    L0_TOL_ABSOLUTE): an entry v is nonzero iff |v| > tau, and two values
  *    a, b are equal iff |a - b| <= tau (tol = 0 is exact equality).
@@ -76,7 +80,8 @@ typedef enum {
     L0_DEV_BAD_INDEX = 16,   /* a row index outside [0, m) (when checked) */
     L0_DEV_NONFINITE_Y = 17, /* y holds NaN or Inf */
     L0_DEV_ABORTED = 19,     /* the device loop timed out waiting for itself */
-    L0_DEV_BAD_WEIGHT = 20   /* a column weight is zero, negative or not finite */
+    L0_DEV_BAD_WEIGHT = 20,  /* a column weight is zero, negative or not finite */
+    L0_DEV_REPEATED_ROW = 21 /* a column lists one row twice (A must be binary, Definition 2.2) */
 } l0_outcome;
 
 typedef enum {
@@ -148,7 +153,8 @@ const char* l0_status_string(int32_t code);
  * The library allocates and frees its workspace on `stream`
  * (hipMallocAsync/hipFreeAsync).  Every row index is range-checked on the
  * device before use; an index outside [0, m) ends the solve with
- * L0_DEV_BAD_INDEX and leaves x_out zero.
+ * L0_DEV_BAD_INDEX, a column with a repeated row with L0_DEV_REPEATED_ROW,
+ * both leaving x_out zero.
  */
 l0_status l0_decode(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y,
                     double alpha, int32_t max_iter, double tol, double* x_out,
@@ -185,8 +191,10 @@ typedef struct l0_matrix_s* l0_matrix;
 /*
  * Build a prepared matrix from col_idx (as l0_decode); the work is enqueued
  * on `stream` and col_idx may be released once the stream has passed it.
- * Row indices are range-checked; solves on a matrix with a bad index end with
- * L0_DEV_BAD_INDEX.  *out receives the handle (host object).
+ * Row indices are range-checked and each column's rows checked for
+ * repeats; solves on a matrix with a bad index end with L0_DEV_BAD_INDEX,
+ * on one with a repeated row with L0_DEV_REPEATED_ROW.  *out receives the
+ * handle (host object).
  */
 l0_status l0_matrix_create(const int32_t* col_idx, int64_t n, int32_t m, int32_t d,
                            l0_matrix* out, hipStream_t stream);
@@ -289,7 +297,8 @@ size_t l0_batch_workspace_bytes(const l0_problem* probs, int32_t count, const l0
  * Workspace: device memory of at least l0_batch_workspace_bytes, 256-byte
  * aligned, caller-owned.  Every instance is validated on the host first
  * (L0_ERR_ARG names no instance; check them individually to find it).
- * Row-index and non-finite-y problems are per-instance outcomes.
+ * Row-index (out of range or repeated in a column) and non-finite-y
+ * problems are per-instance outcomes.
  */
 l0_status l0_decode_batched(const l0_problem* probs, int32_t count, const l0_batch_opts* opts,
                             l0_result* results, void* workspace, size_t ws_bytes, hipStream_t stream);

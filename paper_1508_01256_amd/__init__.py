@@ -27,8 +27,10 @@ L0_OK, L0_ERR_ARG, L0_ERR_OOM, L0_ERR_HIP, L0_ERR_WORKSPACE = 0, 1, 2, 3, 4
 # outcomes (written on the device)
 L0_CONVERGED, L0_STALLED, L0_MAX_ITER = 0, 1, 2
 L0_DEV_BAD_INDEX, L0_DEV_NONFINITE_Y, L0_DEV_ABORTED, L0_DEV_BAD_WEIGHT = 16, 17, 19, 20
+L0_DEV_REPEATED_ROW = 21
 OUTCOME_NAMES = {0: "CONVERGED", 1: "STALLED", 2: "MAX_ITER", 16: "DEV_BAD_INDEX",
-                 17: "DEV_NONFINITE_Y", 19: "DEV_ABORTED"}
+                 17: "DEV_NONFINITE_Y", 19: "DEV_ABORTED", 20: "DEV_BAD_WEIGHT",
+                 21: "DEV_REPEATED_ROW"}
 # rules and tolerance modes
 L0_RULE_L0DEC, L0_RULE_MODE, L0_RULE_SHIFTED_L0DEC, L0_RULE_SHIFTED_MODE = 0, 1, 2, 3
 L0_TOL_RELATIVE, L0_TOL_ABSOLUTE = 0, 1
@@ -287,11 +289,12 @@ def new_result(device="cuda"):
 def decode(col_idx, y, n, m, d, alpha=None, *, max_iter=100, tol=1e-10, rule=L0_RULE_L0DEC,
            tol_mode=L0_TOL_RELATIVE, x_init=None, weights=None, want_trace=True):
     """Decode y = A x on the GPU via l0_decode_ex (column weights of a
-    column-scaled A in `weights`, a device float64 tensor, or None); returns a
+    column-scaled A in `weights`, a device float64 tensor, or None); alpha
+    defaults to max(ceil(d/2), 2), inside (1, d] for every d >= 2.  Returns a
     dict with x (device tensor), iters, outcome, final_nnz, support_size,
     updates, trace, tsize."""
     dev = y.device
-    alpha = float(math.ceil(d / 2)) if alpha is None else float(alpha)
+    alpha = float(max(math.ceil(d / 2), 2)) if alpha is None else float(alpha)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     trace = torch.full((max_iter + 1,), -1, dtype=torch.int32, device=dev) if want_trace else None
     tsize = torch.zeros(max(max_iter, 1), dtype=torch.int64, device=dev) if want_trace else None

@@ -1,15 +1,20 @@
 """Compile the HIP decoder library ``libl0decode.so`` for gfx950, in-tree.
 
-hipcc cross-compiles for gfx950 without a GPU.  Floating-point contraction is
-off (every sum and difference the decoder tests for equality is one IEEE-754
-binary64 operation, as in the CPU oracle), and the packed-FP32 instructions
-are disabled for all device code.
+hipcc cross-compiles for gfx950 without a GPU.  Each source is compiled to
+an object of its own (in parallel; every kernel is launched from the file
+that defines it or through a host function of that file, so no relocatable
+device code is needed), then the objects are linked into the library.
+Floating-point contraction is off (every sum and difference the decoder
+tests for equality is one IEEE-754 binary64 operation, as in the CPU
+oracle), and the packed-FP32 instructions are disabled for all device code.
 """
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -20,7 +25,7 @@ SOURCES = ["l0_kernels.hip", "l0_batch.hip", "l0_api.hip", "l0_server.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC",
     f"--offload-arch={ARCH}",
     "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -34,12 +39,23 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     """Compile every source into libl0decode.so (always recompiles)."""
-    out_tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}",
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", out_tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    with tempfile.TemporaryDirectory(prefix="l0build") as tmp:
+        def compile_one(src):
+            obj = os.path.join(tmp, src + ".o")
+            cmd = [hipcc(), *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-c", os.path.join(CSRC, src),
+                   "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.run(cmd, check=True)
+            return obj
+
+        with ThreadPoolExecutor(len(SOURCES)) as pool:
+            objs = list(pool.map(compile_one, SOURCES))
+        out_tmp = LIB + ".tmp"
+        cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", out_tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     os.replace(out_tmp, LIB)
     return LIB
 

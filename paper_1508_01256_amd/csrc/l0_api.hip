@@ -113,7 +113,7 @@ l0::MatrixView carve_matrix(char* base, int64_t n, int32_t m, int32_t d) {
     v.soa = p;                                    p += b.soa;
     v.row_off = reinterpret_cast<int32_t*>(p);   p += b.row_off;
     v.deg = reinterpret_cast<int32_t*>(p);       p += b.deg;
-    v.bad_index = reinterpret_cast<int32_t*>(p);
+    v.bad_input = reinterpret_cast<int32_t*>(p);
     return v;
 }
 
@@ -153,7 +153,7 @@ l0_status run_solve(const l0::MatrixView& A, const double* y, double alpha, int3
     q.compact = A.compact;
     q.soa = A.soa;
     q.row_off = A.row_off;
-    q.bad_index = A.bad_index;
+    q.bad_input = A.bad_input;
     q.y = y;
     q.tol = tol;
     q.a = static_cast<int32_t>(std::ceil(alpha));
@@ -220,6 +220,7 @@ const char* l0_status_string(int32_t code) {
         case L0_DEV_NONFINITE_Y: return "L0_DEV_NONFINITE_Y";
         case L0_DEV_ABORTED: return "L0_DEV_ABORTED";
         case L0_DEV_BAD_WEIGHT: return "L0_DEV_BAD_WEIGHT";
+        case L0_DEV_REPEATED_ROW: return "L0_DEV_REPEATED_ROW";
         default: return "unknown";
     }
 }
@@ -250,19 +251,31 @@ l0_status l0_decode_ex(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, 
     return run_solve(A, y, alpha, max_iter, tol, x_out, opts, res_out, nullptr, sws, stream, clear.p != nullptr);
 }
 
-l0_status l0_decode(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y,
-                    double alpha, int32_t max_iter, double tol, double* x_out,
-                    int32_t* iters_out, hipStream_t stream) {
-    if (!sizes_ok(n, m, d) || !solve_args_ok(alpha, d, max_iter, tol)) return L0_ERR_ARG;
-    if (!buffer_ok(col_idx, static_cast<size_t>(n) * d * sizeof(int32_t))) return L0_ERR_ARG;
-    if (!common_buffers_ok(n, m, max_iter, y, x_out, nullptr)) return L0_ERR_ARG;
-    if (!buffer_ok(iters_out, sizeof(int32_t))) return L0_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// Host checks of l0_decode's arguments (and of its allocation-free variant).
+bool plain_args_ok(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y, double alpha,
+                   int32_t max_iter, double tol, double* x_out, int32_t* iters_out) {
+    if (!sizes_ok(n, m, d) || !solve_args_ok(alpha, d, max_iter, tol)) return false;
+    if (!buffer_ok(col_idx, static_cast<size_t>(n) * d * sizeof(int32_t))) return false;
+    if (!common_buffers_ok(n, m, max_iter, y, x_out, nullptr)) return false;
+    return buffer_ok(iters_out, sizeof(int32_t));
+}
+
+// Workspace of one plain decode: matrix, solve, then the device result.
+size_t plain_workspace_bytes(int64_t n, int32_t m, int32_t d, int32_t max_iter) {
+    return l0::matrix_layout(n, m, d).total + l0::solve_layout(n, m, d, max_iter).total +
+           l0::align256(sizeof(l0_result));
+}
+
+// Enqueue a plain decode in the workspace at base (need bytes, laid out as
+// plain_workspace_bytes says); nothing in it needs to be initialised.
+l0_status plain_decode_in(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y, double alpha,
+                          int32_t max_iter, double tol, double* x_out, int32_t* iters_out, char* base, size_t need,
+                          hipStream_t stream) {
     const size_t mat = l0::matrix_layout(n, m, d).total;
-    const size_t need = mat + l0::solve_layout(n, m, d, max_iter).total + l0::align256(sizeof(l0_result));
-    void* ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, need, stream);
-    if (e != hipSuccess) return from_hip(e);
-    char* base = static_cast<char*>(ws);
     const l0::MatrixView A = carve_matrix(base, n, m, d);
     l0_result* res = reinterpret_cast<l0_result*>(base + need - l0::align256(sizeof(l0_result)));
     const l0::ZeroSpan clear = one_shot_clear(base + mat, n, m, d, max_iter);
@@ -270,6 +283,23 @@ l0_status l0_decode(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, con
     if (st == L0_OK)
         st = run_solve(A, y, alpha, max_iter, tol, x_out, nullptr, res, iters_out, base + mat, stream,
                        clear.p != nullptr);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+l0_status l0_decode(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y,
+                    double alpha, int32_t max_iter, double tol, double* x_out,
+                    int32_t* iters_out, hipStream_t stream) {
+    if (!plain_args_ok(col_idx, n, m, d, y, alpha, max_iter, tol, x_out, iters_out)) return L0_ERR_ARG;
+    const size_t need = plain_workspace_bytes(n, m, d, max_iter);
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, need, stream);
+    if (e != hipSuccess) return from_hip(e);
+    l0_status st = plain_decode_in(col_idx, n, m, d, y, alpha, max_iter, tol, x_out, iters_out,
+                                   static_cast<char*>(ws), need, stream);
     e = hipFreeAsync(ws, stream);
     if (st == L0_OK && e != hipSuccess) st = from_hip(e);
     return st;

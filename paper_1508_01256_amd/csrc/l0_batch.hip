@@ -608,34 +608,59 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
     bool alive = team_sync(tm, L);
 
     // --- row degrees -> row_off (exclusive scan), counted in LDS one range
-    //     of words_cap rows at a time over this member's share of the index
-    //     stream, read kHistUnroll independent loads per thread at a time; a
-    //     team adds its counts in slot_cnt and the leader scans.  Every row
-    //     index is range-checked in the first pass.
+    //     of words_cap rows at a time over this member's share of the
+    //     columns; a team adds its counts in slot_cnt and the leader scans.
+    //     Each wave reads 64-column groups as the vote does (D coalesced
+    //     loads, transposed through its LDS staging area, two groups in
+    //     flight), so every lane holds one column's rows: the first pass
+    //     range-checks every row and checks that no column lists a row twice.
     const int hcap = bp.words_cap;
     const lptr<int> hist = (lptr<int>)L.words;
-    constexpr int kHistUnroll = 16;
-    const int64_t e_lo = nd * rank / tsize, e_hi = nd * (rank + 1) / tsize;
+    const int lane = tid & 63, nw = nthr >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const lptr<int> stage = L.stage + wid * (64 * D);
+    const int64_t ngroups = (n + 63) >> 6;
+    const int64_t g_first = static_cast<int64_t>(rank) * nw + wid, g_stride = static_cast<int64_t>(tsize) * nw;
     int bad_idx = 0;
     int carry = 0;
     for (int lo = 0; alive && lo < m; lo += hcap) {
         const int len = min(hcap, m - lo);
         for (int i = tid; i < len; i += nthr) hist[i] = 0;
         __syncthreads();
-        for (int64_t base = e_lo; base < e_hi; base += static_cast<int64_t>(nthr) * kHistUnroll) {
-            int rows[kHistUnroll];
+        // one group: stage, read back this lane's column, count its rows
+        auto count_group = [&](const int (&buf)[D], int64_t g) {
 #pragma unroll
-            for (int u = 0; u < kHistUnroll; ++u) {
-                const int64_t e = base + static_cast<int64_t>(u) * nthr + tid;
-                rows[u] = col_idx[e < e_hi ? e : e_hi - 1];
+            for (int k = 0; k < D; ++k) stage[k * 64 + lane] = buf[k];
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+            __builtin_amdgcn_wave_barrier();
+            int r[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) r[t] = stage[lane * D + t];
+            // every lane has read its column before the next group's stores
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            __builtin_amdgcn_wave_barrier();
+            const bool col = g * 64 + lane < n;  // slots past the last column hold no column
+            if (lo == 0 && col) {
+#pragma unroll
+                for (int t = 0; t < D; ++t)
+                    if (r[t] < 0 || r[t] >= m) bad_idx |= kErrBadIndex;
+                if (has_repeat<D>(r)) bad_idx |= kErrRepeatedRow;
             }
 #pragma unroll
-            for (int u = 0; u < kHistUnroll; ++u) {
-                const int64_t e = base + static_cast<int64_t>(u) * nthr + tid;
-                const int rel = rows[u] - lo;
-                if (lo == 0) bad_idx |= rows[u] < 0 || rows[u] >= m;
-                if (e < e_hi && rel >= 0 && rel < len) fetch_add(&hist[rel], 1);
+            for (int t = 0; t < D; ++t) {
+                const int rel = r[t] - lo;
+                if (col && rel >= 0 && rel < len) fetch_add(&hist[rel], 1);
             }
+        };
+        int ga[D], gb[D];
+        load_group<D>(col_idx, g_first, nd, lane, ga);
+        load_group<D>(col_idx, g_first + g_stride, nd, lane, gb);
+        for (int64_t g = g_first; g < ngroups; g += 2 * g_stride) {
+            count_group(ga, g);
+            load_group<D>(col_idx, g + 2 * g_stride, nd, lane, ga);
+            if (g + g_stride >= ngroups) break;
+            count_group(gb, g + g_stride);
+            load_group<D>(col_idx, g + 3 * g_stride, nd, lane, gb);
         }
         __syncthreads();
         if (tsize == 1) {
@@ -646,8 +671,13 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         }
         __syncthreads();
     }
-    bad_idx = wg_sum(bad_idx, L.red);
-    if (tid == 0 && bad_idx) __hip_atomic_fetch_or(&tm.ctl->bad, kErrBadIndex, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the error bits of every wave (an OR of per-wave ORs)
+    {
+        int wbad = bad_idx;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) wbad |= __shfl_xor(wbad, off);
+        if (lane == 0 && wbad) __hip_atomic_fetch_or(&tm.ctl->bad, wbad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (tsize > 1) {
         alive = alive && team_sync(tm, L);
         if (alive && lead) {

@@ -36,7 +36,7 @@ struct MatrixView {
     void* soa;
     int32_t* row_off;   // int32[m+1]
     int32_t* deg;       // int32[m] scratch for the degree histogram
-    int32_t* bad_index; // int32[1]: nonzero when a row index was out of range
+    int32_t* bad_input; // int32[1]: kErrBadIndex / kErrRepeatedRow bits found while repacking
 };
 
 struct MatrixBuffers {
@@ -46,13 +46,28 @@ MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d);
 
 // Input errors found on the device, as bits of a flag word (several may be
 // found at once); the outcome reported is the first of: row index out of
-// range, non-finite y, column weight not positive and finite.
+// range, a row listed twice in one column, non-finite y, column weight not
+// positive and finite.
 constexpr int kErrNonfiniteY = 1;
 constexpr int kErrBadIndex = 2;
 constexpr int kErrBadWeight = 4;
+constexpr int kErrRepeatedRow = 8;
 __host__ __device__ inline int error_outcome(int flags) {
     return (flags & kErrBadIndex) ? L0_DEV_BAD_INDEX
+         : (flags & kErrRepeatedRow) ? L0_DEV_REPEATED_ROW
          : (flags & kErrNonfiniteY) ? L0_DEV_NONFINITE_Y : L0_DEV_BAD_WEIGHT;
+}
+
+// True when two of the d row indices r[0..D) are equal (a column of a
+// binary A lists each of its rows once, Definition 2.2).
+template <int D>
+__host__ __device__ inline bool has_repeat(const int (&r)[D]) {
+    bool rep = false;
+#pragma unroll
+    for (int t = 1; t < D; ++t)
+#pragma unroll
+        for (int u = 0; u < t; ++u) rep |= r[u] == r[t];
+    return rep;
 }
 
 // A usable column weight: positive and finite.
@@ -93,7 +108,7 @@ struct SolveParams {
     int32_t compact;
     const void* soa;
     const int32_t* row_off;
-    const int32_t* bad_index;
+    const int32_t* bad_input;
     const double* y;
     double tol;
     int32_t a;          // ceil(alpha)

@@ -525,7 +525,10 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
                           static_cast<unsigned long long>(__double_as_longlong(lmax)));
         }
         if (wave_count(bad != 0) && (tid & 63) == 0) atomicOr(&c->err, kErrNonfiniteY);
-        if (gtid == 0 && *p.bad_index) atomicOr(&c->err, kErrBadIndex);
+        if (gtid == 0) {
+            const int mb = *p.bad_input;
+            if (mb) atomicOr(&c->err, mb);
+        }
     }
     if (!grid_sync(c, site, limit, p.timeline)) {
         if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
@@ -674,7 +677,8 @@ __global__ void zero_ints(int32_t* p, int64_t count) {
 }
 
 // Repack col_idx (each column's d rows contiguous) into the tiled neighbour
-// planes, check every row index, and count row degrees (LDS histogram when m
+// planes, check every row index and that no column lists a row twice, and
+// count row degrees (LDS histogram when m
 // fits, else global atomics).  A group is 64 columns: their 64*D contiguous
 // indices arrive by D coalesced loads, go through the wave's LDS staging area
 // and leave as D contiguous 64-entry runs, one per neighbour plane.  Each wave
@@ -732,7 +736,7 @@ __global__ void __launch_bounds__(1024) repack_kernel(const int32_t* col_idx, Ma
                 const int row = v[gi][k];
                 const bool inside = e0 + k * 64 < nd;
                 const bool ok = static_cast<unsigned>(row) < m;
-                bad |= inside && !ok;
+                if (inside && !ok) bad |= kErrBadIndex;
                 if (inside && ok) {
                     if (LDS_HIST) atomicAdd(&hist[row], 1);
                     else atomicAdd(&A.deg[row], 1);
@@ -746,9 +750,15 @@ __global__ void __launch_bounds__(1024) repack_kernel(const int32_t* col_idx, Ma
             __builtin_amdgcn_wave_barrier();
             const int64_t tile = g / (kTile / 64);
             const int c = static_cast<int>(g % (kTile / 64)) * 64 + lane;
+            int rr[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) rr[t] = stage[lane * D + t];
+            // column g*64 + lane lists a row twice (columns past n hold only
+            // zeros and are not checked)
+            if (g * 64 + lane < A.n && has_repeat<D>(rr)) bad |= kErrRepeatedRow;
             IT out[D];
 #pragma unroll
-            for (int t = 0; t < D; ++t) out[t] = static_cast<IT>(stage[lane * D + t]);
+            for (int t = 0; t < D; ++t) out[t] = static_cast<IT>(rr[t]);
             // every lane has read its entries before the next group's stores
             __builtin_amdgcn_s_waitcnt(0xC07F);
             __builtin_amdgcn_wave_barrier();
@@ -757,7 +767,7 @@ __global__ void __launch_bounds__(1024) repack_kernel(const int32_t* col_idx, Ma
             for (int t = 0; t < D; ++t) dst[t * kTile] = out[t];
         }
     }
-    if (bad) atomicExch(A.bad_index, 1);
+    if (bad) atomicOr(A.bad_input, bad);
     if (LDS_HIST) {
         __syncthreads();
         for (int i = threadIdx.x; i < A.m; i += blockDim.x)
@@ -878,11 +888,11 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s,
     const int cus = device_cus();
     // the degree counts and the bad-index flag follow each other in the
     // matrix buffers: one fill clears both
-    if (A.bad_index > A.deg) {
-        hipLaunchKernelGGL(zero_ints, dim3(256), dim3(256), 0, s, A.deg, static_cast<int64_t>(A.bad_index - A.deg) + 1);
+    if (A.bad_input > A.deg) {
+        hipLaunchKernelGGL(zero_ints, dim3(256), dim3(256), 0, s, A.deg, static_cast<int64_t>(A.bad_input - A.deg) + 1);
     } else {
         hipLaunchKernelGGL(zero_ints, dim3(256), dim3(256), 0, s, A.deg, static_cast<int64_t>(A.m));
-        hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, A.bad_index, int64_t(1));
+        hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, A.bad_input, int64_t(1));
     }
     const size_t hist_bytes = static_cast<size_t>(A.m) * sizeof(int);
     const size_t stage_bytes = static_cast<size_t>(kRepackWaves) * 64 * D * sizeof(int);

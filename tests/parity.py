@@ -37,13 +37,9 @@ def gpu_run(n, m, d, col, y, alpha, *, max_iter=100, tol=1e-10, rule=l0.L0_RULE_
 
 def oracle_run(n, m, d, col, y, alpha, *, max_iter=100, tol=1e-10, rule=l0.L0_RULE_L0DEC,
                x_init=None, tol_mode=l0.L0_TOL_RELATIVE, w=None):
-    if tol_mode == l0.L0_TOL_ABSOLUTE:
-        # the oracle takes a relative tolerance; convert (exact only when the
-        # division and multiplication round-trip, so tests use powers of two)
-        s = float(np.max(np.abs(y)))
-        tol = tol / s if s > 0 else tol
+    omode = oracle.TOL_ABSOLUTE if tol_mode == l0.L0_TOL_ABSOLUTE else oracle.TOL_RELATIVE
     return oracle.parallel_l0(n, m, d, col, y, alpha, max_iter=max_iter, tol=tol,
-                              rule=RULE_MAP[rule], x_init=x_init, w=w)
+                              rule=RULE_MAP[rule], x_init=x_init, w=w, tol_mode=omode)
 
 
 def assert_parity(g, o, *, label=""):
