@@ -161,6 +161,29 @@ l0_status l0_decode(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, con
                     int32_t* iters_out, hipStream_t stream);
 
 /*
+ * l0_decode without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments and results as l0_decode.  The workspace is
+ * a fixed array of L0_NOALLOC_SCRATCH_BYTES in the library's device memory,
+ * one per device, held until the process ends; nothing is allocated or freed
+ * and no library routine that allocates is called.  Problems whose workspace
+ * (l0_noalloc_workspace_bytes) exceeds that size are refused with
+ * L0_ERR_WORKSPACE before anything is enqueued (at d = 7 about 3 million
+ * columns fit).  Every call on a device uses that device's one array: calls
+ * that overlap on one device (several streams, or host threads) race and
+ * must not be issued; calls ordered on one stream are safe (each clears what
+ * it needs before use).
+ */
+#define L0_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+l0_status l0_decode_noalloc(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y,
+                            double alpha, int32_t max_iter, double tol, double* x_out,
+                            int32_t* iters_out, hipStream_t stream);
+
+/* Bytes of the fixed array l0_decode_noalloc needs for a problem of this
+ * shape (0 for invalid sizes); at most L0_NOALLOC_SCRATCH_BYTES is served. */
+size_t l0_noalloc_workspace_bytes(int64_t n, int32_t m, int32_t d, int32_t max_iter);
+
+/*
  * Bytes of device workspace l0_decode_ex needs for one problem of this shape
  * (0 for invalid sizes).
  */

@@ -40,7 +40,8 @@ EXPORTED = ("l0_version", "l0_status_string", "l0_decode", "l0_workspace_bytes",
             "l0_matrix_create", "l0_matrix_destroy", "l0_solve_workspace_bytes", "l0_solve", "l0_set_solve_admission",
             "l0_batch_workspace_bytes", "l0_decode_batched", "l0_batch_autotune",
             "l0_server_create", "l0_server_submit", "l0_server_poll", "l0_server_drain",
-            "l0_server_outstanding", "l0_server_destroy")
+            "l0_server_outstanding", "l0_server_destroy", "l0_decode_noalloc",
+            "l0_noalloc_workspace_bytes")
 
 
 class LibraryMissing(RuntimeError):
@@ -125,7 +126,10 @@ def lib():
         L.l0_server_outstanding.argtypes, L.l0_server_outstanding.restype = [P], I64
         L.l0_server_destroy.argtypes = [P]
         L.l0_set_solve_admission.argtypes = [I32, I32]
-        for f in ("l0_decode", "l0_decode_ex", "l0_matrix_create", "l0_matrix_destroy", "l0_solve",
+        L.l0_decode_noalloc.argtypes = [P, I64, I32, I32, P, F64, I32, F64, P, P, P]
+        L.l0_noalloc_workspace_bytes.argtypes = [I64, I32, I32, I32]
+        L.l0_noalloc_workspace_bytes.restype = SZ
+        for f in ("l0_decode", "l0_decode_noalloc", "l0_decode_ex", "l0_matrix_create", "l0_matrix_destroy", "l0_solve",
                   "l0_set_solve_admission",
                   "l0_decode_batched", "l0_batch_autotune", "l0_server_create", "l0_server_submit",
                   "l0_server_drain", "l0_server_destroy"):
@@ -162,6 +166,18 @@ def l0_status_string(code: int) -> str:
 def l0_decode(col_idx, n, m, d, y, alpha, max_iter, tol, x_out, iters_out) -> int:
     return lib().l0_decode(_ptr(col_idx), n, m, d, _ptr(y), float(alpha), max_iter, float(tol),
                            _ptr(x_out), _ptr(iters_out), _stream())
+
+
+def l0_decode_noalloc(col_idx, n, m, d, y, alpha, max_iter, tol, x_out, iters_out) -> int:
+    return lib().l0_decode_noalloc(_ptr(col_idx), n, m, d, _ptr(y), float(alpha), max_iter, float(tol),
+                                   _ptr(x_out), _ptr(iters_out), _stream())
+
+
+def l0_noalloc_workspace_bytes(n, m, d, max_iter) -> int:
+    return lib().l0_noalloc_workspace_bytes(n, m, d, max_iter)
+
+
+L0_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 def l0_workspace_bytes(n, m, d, max_iter) -> int:

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "l0_internal.h"
@@ -303,6 +304,67 @@ l0_status l0_decode(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, con
     e = hipFreeAsync(ws, stream);
     if (st == L0_OK && e != hipSuccess) st = from_hip(e);
     return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// plain decode without any allocation: the workspace is a fixed device array
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// The array the allocation-free decode works in, one copy per device (each
+// device holds its own until the process ends).  Its name is a host-side
+// stand-in: host code uses only the device address taken below.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static_assert(kScratchBytes == L0_NOALLOC_SCRATCH_BYTES, "the header states the scratch size");
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, taken once per
+// device (with that device current); nullptr if it cannot be had.
+char* scratch_on_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return static_cast<char*>(g_scratch_ptr[dev]);
+}
+
+}  // namespace
+
+extern "C" {
+
+l0_status l0_decode_noalloc(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, const double* y,
+                            double alpha, int32_t max_iter, double tol, double* x_out, int32_t* iters_out,
+                            hipStream_t stream) {
+    if (!plain_args_ok(col_idx, n, m, d, y, alpha, max_iter, tol, x_out, iters_out)) return L0_ERR_ARG;
+    const size_t need = plain_workspace_bytes(n, m, d, max_iter);
+    if (need > kScratchBytes) return L0_ERR_WORKSPACE;
+    char* base = scratch_on_current_device();
+    if (!base) return L0_ERR_HIP;
+    // every part of the workspace that must start at zero is cleared by the
+    // decode's own fill kernels (no memset)
+    return plain_decode_in(col_idx, n, m, d, y, alpha, max_iter, tol, x_out, iters_out, base, need, stream);
+}
+
+size_t l0_noalloc_workspace_bytes(int64_t n, int32_t m, int32_t d, int32_t max_iter) {
+    if (!sizes_ok(n, m, d) || max_iter < 0 || max_iter > kMaxIterCap) return 0;
+    return plain_workspace_bytes(n, m, d, max_iter);
 }
 
 l0_status l0_matrix_create(const int32_t* col_idx, int64_t n, int32_t m, int32_t d, l0_matrix* out,
