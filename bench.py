@@ -15,7 +15,7 @@ stream) over repeated l0_solve calls on the prepared matrix.  Its algorithmic
 bytes per launch follow the method's per-pass figure: 8n (x_hat cleared) plus,
 per vote pass, 4nd (the column-index stream at 4 bytes an index) + 16m (y
 read, r written) plus (16 + 4d) per applied update.  The library stores
-16-bit indices when m <= 36864, so the bytes it actually streams are fewer;
+16-bit indices when m <= 65536, so the bytes it actually streams are fewer;
 that figure is reported beside it ("stored_bytes_per_launch"), as are the
 rocprofv3 counter bytes.  The CPU baseline is the FP64 oracle (one thread)
 on one full decode of the same instance.
@@ -123,9 +123,21 @@ def passes_of(iters, outcome):
 
 
 def index_bytes(m):
-    """Bytes per stored row index: the library keeps 16-bit rows when the rows'
-    bucket words fit in LDS (4 m <= 144 KiB), else 32-bit rows."""
-    return 2 if 4 * m <= 144 * 1024 else 4
+    """Bytes per stored row index: the library keeps 16-bit rows when every
+    row fits (m <= 65536), else 32-bit rows."""
+    return 2 if m <= 65536 else 4
+
+
+def word_mode(m):
+    """Where the vote keeps the bucket words (as the library decides):
+    1 = 32-bit in LDS, 2 = 16-bit folded in LDS, 3 = 8-bit folded in LDS,
+    0 = 32-bit gathered from global memory."""
+    lds = 144 * 1024
+    if 4 * m <= lds:
+        return 1
+    if m <= 65536 and 2 * m <= lds:
+        return 2
+    return 3 if m <= lds else 0
 
 
 def algorithmic_bytes(n, m, d, iters, outcome, tsizes, index_width=4):
@@ -289,12 +301,12 @@ def main():
     vote_bytes = index_bytes(m) * n * d
     print(f"[bench] solve kernel avg {solve_avg:.3f} ms (min {min(solve_ms):.3f}) over {args.repeats}; "
           f"passes={passes} trace={tr} tsize={ts}; {achieved:.0f} GB/s algorithmic "
-          f"({stored_gbs:.0f} GB/s of the 16-bit store actually streamed); "
+          f"({stored_gbs:.0f} GB/s of the {8 * index_bytes(m)}-bit store actually streamed); "
           f"prep {prep_ms:.2f} ms", file=sys.stderr, flush=True)
     A.close()
 
     traffic = measured_traffic(args.size)
-    kname = f"l0::solve_kernel<{d},{'true' if index_bytes(m) == 2 else 'false'}>"
+    kname = f"l0::solve_kernel<{d},{word_mode(m)}>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname, "bytes_per_launch": bytes_launch,

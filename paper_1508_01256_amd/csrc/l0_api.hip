@@ -21,7 +21,7 @@ namespace l0 {
 MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d) {
     MatrixBuffers b{};
     const int64_t ntiles = (n + kTile - 1) / kTile;
-    b.soa = align256(static_cast<size_t>(ntiles) * d * kTile * (is_compact(m) ? 2 : 4));
+    b.soa = align256(static_cast<size_t>(ntiles) * d * kTile * (rows16(m) ? 2 : 4));
     b.row_off = align256((static_cast<size_t>(m) + 1) * sizeof(int32_t));
     b.deg = align256(static_cast<size_t>(m) * sizeof(int32_t));
     b.flag = 256;
@@ -35,10 +35,11 @@ SolveBuffers solve_layout(int64_t n, int32_t m, int32_t d, int32_t max_iter) {
     b.counters = align256(2 * (static_cast<size_t>(max_iter) + 2) * sizeof(int32_t));
     b.r = align256(static_cast<size_t>(m) * sizeof(double));
     b.rword = align256(static_cast<size_t>(m) * sizeof(uint32_t));
-    b.slot_cnt = b.slot_sorted = b.aff_flag = b.aff_list = align256(static_cast<size_t>(m) * sizeof(int32_t));
+    b.slot_cnt = b.slot_sorted = b.aff_flag = align256(static_cast<size_t>(m) * sizeof(int32_t));
+    b.aff_list = align256(2 * static_cast<size_t>(m) * sizeof(int32_t));
     b.member = align256(static_cast<size_t>((n + 31) / 32) * sizeof(uint32_t));
     b.slots = align256(static_cast<size_t>(n) * d * sizeof(int32_t));
-    b.total = b.ctrl + b.counters + b.r + b.rword + 4 * b.slot_cnt + b.member + b.slots;
+    b.total = b.ctrl + b.counters + b.r + b.rword + 3 * b.slot_cnt + b.aff_list + b.member + b.slots;
     return b;
 }
 
@@ -110,7 +111,7 @@ l0::MatrixView carve_matrix(char* base, int64_t n, int32_t m, int32_t d) {
     v.d = d;
     v.ntiles = (n + l0::kTile - 1) / l0::kTile;
     char* p = base;
-    v.compact = l0::is_compact(m) ? 1 : 0;
+    v.rows16 = l0::rows16(m) ? 1 : 0;
     v.soa = p;                                    p += b.soa;
     v.row_off = reinterpret_cast<int32_t*>(p);   p += b.row_off;
     v.deg = reinterpret_cast<int32_t*>(p);       p += b.deg;
@@ -125,7 +126,7 @@ void carve_solve(l0::SolveParams& q, char* base, int64_t n, int32_t m, int32_t d
     q.tcount = reinterpret_cast<int32_t*>(p);
     q.affc = q.tcount + (max_iter + 2);                  p += b.counters;
     q.r = reinterpret_cast<double*>(p);                  p += b.r;
-    q.rword = reinterpret_cast<uint32_t*>(p);            p += b.rword;
+    q.rword = p;                                         p += b.rword;
     q.slot_cnt = reinterpret_cast<int32_t*>(p);          p += b.slot_cnt;
     q.slot_sorted = reinterpret_cast<int32_t*>(p);       p += b.slot_sorted;
     q.aff_flag = reinterpret_cast<int32_t*>(p);          p += b.aff_flag;
@@ -151,7 +152,7 @@ l0_status run_solve(const l0::MatrixView& A, const double* y, double alpha, int3
     q.m = A.m;
     q.d = A.d;
     q.ntiles = A.ntiles;
-    q.compact = A.compact;
+    q.wmode = l0::word_mode(A.m);
     q.soa = A.soa;
     q.row_off = A.row_off;
     q.bad_input = A.bad_input;

@@ -148,6 +148,22 @@ L0_HD uint32_t unfold_word(uint16_t h) {
     return (static_cast<uint32_t>(h) & 0x7FFFu) | ((static_cast<uint32_t>(h) & 0x8000u) << 16);
 }
 
+// 8-bit words for LDS copies of up to four times as many rows: bucket bit k
+// goes to bit k mod 7, the zero flag to bit 7.  The same argument as for the
+// 16-bit fold keeps the filter a necessary condition.
+L0_HD uint8_t fold_word8(uint32_t w) {
+    const uint32_t v = w & kBucketBits;
+    uint32_t b = 0u;
+#pragma unroll
+    for (int s = 0; s < 31; s += 7) b |= (v >> s) & 0x7Fu;
+    return static_cast<uint8_t>(b | ((w >> 24) & 0x80u));
+}
+
+// An 8-bit folded word back in the 32-bit layout (zero flag in bit 31).
+L0_HD uint32_t unfold_word8(uint8_t h) {
+    return (static_cast<uint32_t>(h) & 0x7Fu) | ((static_cast<uint32_t>(h) & 0x80u) << 24);
+}
+
 // Bit-sliced population count of D words: c[k] holds bit k of the per-bit-
 // position count.  Full adders (xor / majority) for the common degrees, a
 // ripple-carry accumulation otherwise.

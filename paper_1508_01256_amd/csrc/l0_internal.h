@@ -14,25 +14,45 @@ constexpr int kDMax = 20;
 constexpr int kTile = 256;          // columns per tile of the repacked index store
 constexpr int kBlock = 1024;        // threads per workgroup of the solve kernel
 constexpr int kWaves = kBlock / 64; // wavefronts per workgroup
-// Row bucket words staged in LDS when 4*m fits under this (gfx950 has 160 KiB
-// per CU; the rest holds the per-workgroup queue and reduction scratch).  Such
-// "compact" problems (m <= 36864) also store row indices as 16 bits.
+// LDS bytes for the row bucket words of the vote (gfx950 has 160 KiB per CU;
+// the rest holds the per-workgroup queue and reduction scratch).
 constexpr size_t kLdsWordBytes = 144 * 1024;
-inline bool is_compact(int32_t m) { return static_cast<size_t>(m) * 4 <= kLdsWordBytes; }
+
+// How a solve keeps the bucket words its vote gathers:
+//   kWordsLds32   m <= 36864:  32-bit words in LDS
+//   kWordsLds16   m <= 65536:  16-bit folded words in LDS
+//   kWordsLds8    m <= 147456: 8-bit folded words in LDS
+//   kWordsGlobal  larger m:    32-bit words gathered from global memory
+// The global copy of the words (maintained by the residual phase) has the
+// same width as the LDS copy.
+constexpr int kWordsGlobal = 0;
+constexpr int kWordsLds32 = 1;
+constexpr int kWordsLds16 = 2;
+constexpr int kWordsLds8 = 3;
+constexpr int word_bytes(int wm) { return wm == kWordsLds16 ? 2 : (wm == kWordsLds8 ? 1 : 4); }
+inline int word_mode(int32_t m) {
+    const size_t mm = static_cast<size_t>(m);
+    if (mm * 4 <= kLdsWordBytes) return kWordsLds32;
+    if (mm <= 65536 && mm * 2 <= kLdsWordBytes) return kWordsLds16;
+    if (mm <= kLdsWordBytes) return kWordsLds8;
+    return kWordsGlobal;
+}
+// Row indices are stored as 16 bits when every row fits.
+inline bool rows16(int32_t m) { return m <= 65536; }
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Device-resident prepared matrix (layout of the repacked column-index store):
 //   soa[(tile*d + t)*kTile + c] = row of column tile*kTile + c, t-th neighbour
-// as uint16 when compact, else int32 (columns past n hold row 0 and are never
-// scored); row_off[i] .. row_off[i+1] is row i's capacity region in the
+// as uint16 when rows16(m), else int32 (columns past n hold row 0 and are
+// never scored); row_off[i] .. row_off[i+1] is row i's capacity region in the
 // per-row support lists (its degree in A).
 struct MatrixView {
     int64_t n;
     int32_t m;
     int32_t d;
     int64_t ntiles;
-    int32_t compact;    // is_compact(m): 16-bit rows, bucket words in LDS
+    int32_t rows16;     // rows16(m): 16-bit row indices
     void* soa;
     int32_t* row_off;   // int32[m+1]
     int32_t* deg;       // int32[m] scratch for the degree histogram
@@ -105,7 +125,7 @@ struct SolveParams {
     int32_t m;
     int32_t d;
     int64_t ntiles;
-    int32_t compact;
+    int32_t wmode;      // word_mode(m) (fixes the row width too)
     const void* soa;
     const int32_t* row_off;
     const int32_t* bad_input;
@@ -129,11 +149,11 @@ struct SolveParams {
     int32_t* tcount;     // int32[max_iter+2]
     int32_t* affc;       // int32[max_iter+2]
     double* r;
-    uint32_t* rword;     // uint32[m]: bucket word of each residual entry
+    void* rword;         // m bucket words of the residual entries, word_bytes(wmode) each
     int32_t* slot_cnt;
     int32_t* slot_sorted;
     int32_t* aff_flag;
-    int32_t* aff_list;
+    int32_t* aff_list;   // int32[2m]: touched rows of even / odd iterations
     uint32_t* member;
     int32_t* slots;
     // the control block and counters are already zero (a one-shot decode

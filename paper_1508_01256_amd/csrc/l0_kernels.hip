@@ -22,6 +22,7 @@
 
 #include <atomic>
 #include <climits>
+#include <type_traits>
 
 #include "l0_internal.h"
 #include "l0_filter.h"
@@ -223,11 +224,37 @@ __device__ __forceinline__ int64_t soa_index(int64_t j, int t, int d) {
 }
 
 // Row index of column j's t-th neighbour in the repacked store (16-bit
-// entries for compact problems, 32-bit otherwise).
-template <bool COMPACT>
+// entries when every row fits, else 32-bit).
+template <bool ROWS16>
 __device__ __forceinline__ int soa_row(const void* soa, int64_t j, int t, int d) {
-    if constexpr (COMPACT) return static_cast<const uint16_t*>(soa)[soa_index(j, t, d)];
+    if constexpr (ROWS16) return static_cast<const uint16_t*>(soa)[soa_index(j, t, d)];
     else return static_cast<const int32_t*>(soa)[soa_index(j, t, d)];
+}
+
+template <int WM>
+struct Words {
+    static constexpr bool kLds = WM != kWordsGlobal;
+    static constexpr bool kRows16 = WM == kWordsLds32 || WM == kWordsLds16;
+    using T = typename std::conditional<WM == kWordsLds16, uint16_t,
+                                        typename std::conditional<WM == kWordsLds8, uint8_t, uint32_t>::type>::type;
+};
+
+// The bucket word of row i in the 32-bit layout, from a word array of mode WM.
+template <int WM>
+__device__ __forceinline__ uint32_t word_at(const void* words, uint32_t i) {
+    using T = typename Words<WM>::T;
+    const T w = static_cast<const T*>(words)[i];
+    if constexpr (WM == kWordsLds16) return unfold_word(w);
+    else if constexpr (WM == kWordsLds8) return unfold_word8(w);
+    else return w;
+}
+
+// Store row i's bucket word (32-bit layout w) in a word array of mode WM.
+template <int WM>
+__device__ __forceinline__ void put_word(void* words, uint32_t i, uint32_t w) {
+    if constexpr (WM == kWordsLds16) static_cast<uint16_t*>(words)[i] = fold_word(w);
+    else if constexpr (WM == kWordsLds8) static_cast<uint8_t*>(words)[i] = fold_word8(w);
+    else static_cast<uint32_t*>(words)[i] = w;
 }
 
 __device__ void write_result(const SolveParams& p, int iters, int outcome, int nnz, int support,
@@ -240,6 +267,38 @@ __device__ void write_result(const SolveParams& p, int iters, int outcome, int n
     if (p.iters_out) *p.iters_out = (outcome < 16) ? iters : -outcome;
 }
 
+// The state apply_update and the residual helpers work on (field names as
+// theirs expect): the touched-row list is the one of the current
+// iteration's parity, so a workgroup still reading the previous iteration's
+// list is never overwritten by one that runs ahead.
+struct SolveState {
+    double* x;
+    const double* w;
+    const double* y;
+    uint32_t* member;
+    int32_t* slot_cnt;
+    int32_t* slot_sorted;
+    int32_t* aff_flag;
+    int32_t* aff_list;
+    const int32_t* row_off;
+    int32_t* slots;
+};
+
+__device__ __forceinline__ SolveState state_of(const SolveParams& p, int l) {
+    SolveState s;
+    s.x = p.x;
+    s.w = p.w;
+    s.y = p.y;
+    s.member = p.member;
+    s.slot_cnt = p.slot_cnt;
+    s.slot_sorted = p.slot_sorted;
+    s.aff_flag = p.aff_flag;
+    s.aff_list = p.aff_list + static_cast<int64_t>(l & 1) * p.m;
+    s.row_off = p.row_off;
+    s.slots = p.slots;
+    return s;
+}
+
 // ---------------------------------------------------------------------------
 // the score of one column (eq. (selection_l0))
 // ---------------------------------------------------------------------------
@@ -247,35 +306,35 @@ __device__ void write_result(const SolveParams& p, int iters, int outcome, int n
 // Exact scoring of one column that passed the bucket filter: its rows come
 // from the repacked index store, its values from the FP64 residual.
 // (Shifted rules: the one candidate of this pass, at position pos.)
-template <int D, bool COMPACT>
-__device__ void score_exact(const SolveParams& p, int l, int64_t j, double tau, int pos) {
+template <int D, bool ROWS16>
+__device__ void score_exact(const SolveParams& p, const SolveState& st, int l, int64_t j, double tau, int pos) {
     int rows[D];
 #pragma unroll
-    for (int t = 0; t < D; ++t) rows[t] = soa_row<COMPACT>(p.soa, j, t, D);
+    for (int t = 0; t < D; ++t) rows[t] = soa_row<ROWS16>(p.soa, j, t, D);
     double v[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) v[t] = p.r[rows[t]];
     double om;
     const bool sel = rule_is_shifted(p.rule) ? exact_score_shifted<D>(v, pos, tau, p.rule, p.a, om)
                                              : exact_score<D>(v, tau, p.rule, p.a, om);
-    if (sel) apply_update<D>(p, &p.tcount[l], &p.ctrl->support, &p.affc[l], j, column_update(p, j, om), rows);
+    if (sel) apply_update<D>(st, &p.tcount[l], &p.ctrl->support, &p.affc[l], j, column_update(st, j, om), rows);
 }
 
 constexpr int kQueue = 2048;  // per-workgroup queue of columns passing the filter
 
 // A chunk is the unit a wave streams: 128 columns (two 16-bit rows per lane
-// and plane) for compact problems, else 64 columns (one 32-bit row per lane).
+// and plane) for 16-bit rows, else 64 columns (one 32-bit row per lane).
 // Each neighbour plane of a chunk is one coalesced 256-byte load.
-template <bool COMPACT>
+template <bool ROWS16>
 struct Chunk {
-    static constexpr uint32_t kCols = COMPACT ? 128 : 64;
+    static constexpr uint32_t kCols = ROWS16 ? 128 : 64;
     static constexpr uint32_t kPerTile = kTile / kCols;
 };
 
-template <int D, bool COMPACT>
+template <int D, bool ROWS16>
 __device__ __forceinline__ void load_chunk(const void* soa, uint32_t g, uint32_t lane, uint32_t (&rows)[D]) {
-    constexpr uint32_t plane = COMPACT ? kTile / 2 : kTile;  // 32-bit words per plane of a tile
-    constexpr uint32_t per = Chunk<COMPACT>::kPerTile;
+    constexpr uint32_t plane = ROWS16 ? kTile / 2 : kTile;  // 32-bit words per plane of a tile
+    constexpr uint32_t per = Chunk<ROWS16>::kPerTile;
     // one base address; the planes are immediate offsets from it
     const uint32_t* __restrict__ q = static_cast<const uint32_t*>(soa) +
                                      (static_cast<uint64_t>(g / per) * (D * plane) + (g % per) * 64u + lane);
@@ -304,24 +363,27 @@ __device__ __forceinline__ void filter_and_queue(const SolveParams& p, const uin
     }
 }
 
-// Filter one chunk whose row indices are in `rows`.
-template <int D, bool COMPACT>
-__device__ __forceinline__ void filter_chunk(const SolveParams& p, const uint32_t* words, const uint32_t (&rows)[D],
+// The rows of half h of a chunk's lane (16-bit rows: two per 32-bit word).
+template <bool ROWS16>
+__device__ __forceinline__ uint32_t chunk_row(uint32_t r, int h) {
+    if constexpr (ROWS16) return h ? (r >> 16) : (r & 0xFFFFu);
+    else return r;
+}
+
+// Filter one chunk whose row indices are in `rows`; `words` is the LDS copy
+// of the bucket words (or the global array for kWordsGlobal).
+template <int D, int WM>
+__device__ __forceinline__ void filter_chunk(const SolveParams& p, const void* words, const uint32_t (&rows)[D],
                                              uint32_t g, uint32_t n, uint32_t lane, int* q_items, int* q_count,
                                              int* q_ovf) {
-    if constexpr (COMPACT) {
+    constexpr bool R16 = Words<WM>::kRows16;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            uint32_t w[D];
-#pragma unroll
-            for (int t = 0; t < D; ++t) w[t] = words[h ? (rows[t] >> 16) : (rows[t] & 0xFFFFu)];
-            filter_and_queue<D>(p, w, g * Chunk<true>::kCols + 2 * lane + h, n, lane, q_items, q_count, q_ovf);
-        }
-    } else {
+    for (int h = 0; h < (R16 ? 2 : 1); ++h) {
         uint32_t w[D];
 #pragma unroll
-        for (int t = 0; t < D; ++t) w[t] = words[rows[t]];
-        filter_and_queue<D>(p, w, g * Chunk<false>::kCols + lane, n, lane, q_items, q_count, q_ovf);
+        for (int t = 0; t < D; ++t) w[t] = word_at<WM>(words, chunk_row<R16>(rows[t], h));
+        const uint32_t j = R16 ? g * Chunk<true>::kCols + 2 * lane + h : g * Chunk<false>::kCols + lane;
+        filter_and_queue<D>(p, w, j, n, lane, q_items, q_count, q_ovf);
     }
 }
 
@@ -338,14 +400,14 @@ __device__ __forceinline__ void filter_chunk(const SolveParams& p, const uint32_
 // cannot wait for a chunk's loads without also waiting for an older claim).
 // l: the iteration (update counters); pos: the position shifted rules try in
 // this pass.
-template <int D, bool COMPACT>
-__device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32_t* lds_w,
-                           int* q_items, int* q_count, int* q_ovf, int pos, unsigned member,
-                           unsigned members) {
+template <int D, int WM>
+__device__ void vote_phase(const SolveParams& p, const SolveState& st, int l, double tau, const void* lds_w,
+                           int* q_items, int* q_count, int* q_ovf, int pos, unsigned member, unsigned members) {
+    constexpr bool R16 = Words<WM>::kRows16;
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t nchunks = static_cast<uint32_t>(p.ntiles) * Chunk<COMPACT>::kPerTile;
+    const uint32_t nchunks = static_cast<uint32_t>(p.ntiles) * Chunk<R16>::kPerTile;
     const uint32_t n = static_cast<uint32_t>(p.n);
-    const uint32_t* __restrict__ words = COMPACT ? lds_w : p.rword;
+    const void* words = Words<WM>::kLds ? lds_w : p.rword;
     const uint32_t stride = members * kWaves;
     const uint32_t first = member * kWaves + (threadIdx.x >> 6);
     // prefetches past the last chunk read the last chunk again (an L2 hit;
@@ -353,15 +415,15 @@ __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32
     const uint32_t last = nchunks - 1;
     uint32_t g = first;
     uint32_t a[D], b[D];
-    load_chunk<D, COMPACT>(p.soa, min(g, last), lane, a);
-    load_chunk<D, COMPACT>(p.soa, min(g + stride, last), lane, b);
+    load_chunk<D, R16>(p.soa, min(g, last), lane, a);
+    load_chunk<D, R16>(p.soa, min(g + stride, last), lane, b);
     while (g < nchunks) {
-        filter_chunk<D, COMPACT>(p, words, a, g, n, lane, q_items, q_count, q_ovf);
-        load_chunk<D, COMPACT>(p.soa, min(g + 2 * stride, last), lane, a);
+        filter_chunk<D, WM>(p, words, a, g, n, lane, q_items, q_count, q_ovf);
+        load_chunk<D, R16>(p.soa, min(g + 2 * stride, last), lane, a);
         g += stride;
         if (g >= nchunks) break;
-        filter_chunk<D, COMPACT>(p, words, b, g, n, lane, q_items, q_count, q_ovf);
-        load_chunk<D, COMPACT>(p.soa, min(g + 2 * stride, last), lane, b);
+        filter_chunk<D, WM>(p, words, b, g, n, lane, q_items, q_count, q_ovf);
+        load_chunk<D, R16>(p.soa, min(g + 2 * stride, last), lane, b);
         g += stride;
     }
     __syncthreads();
@@ -369,21 +431,20 @@ __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32
         p.timeline[3 * p.max_iter + 9 + 3 * l] = static_cast<int64_t>(wall_clock64());
     if (*q_ovf == 0) {
         const int cnt = *q_count;
-        for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D, COMPACT>(p, l, q_items[q], tau, pos);
+        for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D, R16>(p, st, l, q_items[q], tau, pos);
     } else {
         // overflow: every chunk of this wave again, passing columns scored directly
-        constexpr uint32_t kCols = Chunk<COMPACT>::kCols;
+        constexpr uint32_t kCols = Chunk<R16>::kCols;
         for (uint32_t c = first; c < nchunks; c += stride) {
             uint32_t rows[D];
-            load_chunk<D, COMPACT>(p.soa, c, lane, rows);
+            load_chunk<D, R16>(p.soa, c, lane, rows);
 #pragma unroll
-            for (int h = 0; h < (COMPACT ? 2 : 1); ++h) {
+            for (int h = 0; h < (R16 ? 2 : 1); ++h) {
                 uint32_t w[D];
 #pragma unroll
-                for (int t = 0; t < D; ++t)
-                    w[t] = words[COMPACT ? (h ? (rows[t] >> 16) : (rows[t] & 0xFFFFu)) : rows[t]];
-                const uint32_t j = c * kCols + (COMPACT ? 2 * lane + h : lane);
-                if (bucket_filter<D>(w, p.a, p.rule) && j < n) score_exact<D, COMPACT>(p, l, j, tau, pos);
+                for (int t = 0; t < D; ++t) w[t] = word_at<WM>(words, chunk_row<R16>(rows[t], h));
+                const uint32_t j = c * kCols + (R16 ? 2 * lane + h : lane);
+                if (bucket_filter<D>(w, p.a, p.rule) && j < n) score_exact<D, R16>(p, st, l, j, tau, pos);
             }
         }
     }
@@ -394,6 +455,32 @@ __device__ void vote_phase(const SolveParams& p, int l, double tau, const uint32
         if (p.timeline && member == 0)
             p.timeline[3 * p.max_iter + 10 + 3 * l] = static_cast<int64_t>(wall_clock64());
     }
+}
+
+// Copy the global bucket words (mode WM, m of them) into this workgroup's
+// LDS copy: 16-byte loads, four in flight per thread, the tail word by word.
+template <int WM>
+__device__ void stage_words(const SolveParams& p, void* lds_w) {
+    using T = typename Words<WM>::T;
+    const int bytes = p.m * static_cast<int>(sizeof(T));
+    const int n16 = bytes >> 4;
+    const uint4* src4 = static_cast<const uint4*>(p.rword);
+    uint4* dst4 = static_cast<uint4*>(lds_w);
+    const int tid = threadIdx.x;
+    int i = tid;
+    for (; i + 3 * kBlock < n16; i += 4 * kBlock) {
+        const uint4 a0 = src4[i], a1 = src4[i + kBlock];
+        const uint4 a2 = src4[i + 2 * kBlock], a3 = src4[i + 3 * kBlock];
+        dst4[i] = a0;
+        dst4[i + kBlock] = a1;
+        dst4[i + 2 * kBlock] = a2;
+        dst4[i + 3 * kBlock] = a3;
+    }
+    for (; i < n16; i += kBlock) dst4[i] = src4[i];
+    const T* src = static_cast<const T*>(p.rword);
+    T* dst = static_cast<T*>(lds_w);
+    for (int t = ((n16 << 4) / static_cast<int>(sizeof(T))) + tid; t < p.m; t += kBlock) dst[t] = src[t];
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -410,11 +497,12 @@ struct Occ {
     static constexpr int kWavesPerEU = 4;
 };
 
-template <int D, bool COMPACT>
+template <int D, int WM>
 __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(SolveParams p, Admission adm) {
     extern __shared__ uint32_t lds_w[];
     __shared__ int q_items[kQueue];
     __shared__ int q_count, q_ovf;
+    constexpr bool R16 = Words<WM>::kRows16;
     if (threadIdx.x == 0) q_count = q_ovf = 0;
     const int tid = threadIdx.x;
     Ctrl* c = p.ctrl;
@@ -432,12 +520,12 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     if (p.timeline && site.member == 0 && tid == 0)
         p.timeline[3 * p.max_iter + 7] = static_cast<int64_t>(wall_clock64());
 
-    // Without a resume vector and with the bucket words in LDS (y then has
-    // at most 36864 entries), every workgroup derives max |y|, tau, ||y||_0
-    // and all bucket words of r = y from y itself: no grid barrier is needed
+    // Without a resume vector and with 32-bit words in LDS (y then has at
+    // most 36864 entries), every workgroup derives max |y|, tau, ||y||_0 and
+    // all bucket words of r = y from y itself: no grid barrier is needed
     // between the start-up and the first vote, and the first pass stages
     // nothing.
-    const bool local_init = COMPACT && p.x_init == nullptr;
+    const bool local_init = WM == kWordsLds32 && p.x_init == nullptr;
 
     // (The local start reads y before the init below floods the memory
     // system with the stores that clear x_hat.)
@@ -480,7 +568,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             }
         }
         nnz = block_sum(cnt);
-        for (int64_t i = gtid; i < p.m; i += gsize) p.rword[i] = lds_w[i];
+        for (int64_t i = gtid; i < p.m; i += gsize) static_cast<uint32_t*>(p.rword)[i] = lds_w[i];
         if (gtid == 0) __hip_atomic_store(&c->nnz, nnz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // --- init: x_hat, support bitmap, per-row state, max |y|, finiteness of
@@ -552,7 +640,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             atomicOr(&p.member[j >> 5], 1u << (j & 31));
             atomicAdd(&c->support, 1);
             for (int t = 0; t < D; ++t) {
-                const int i = soa_row<COMPACT>(p.soa, j, t, D);
+                const int i = soa_row<R16>(p.soa, j, t, D);
                 const int q = atomicAdd(&p.slot_cnt[i], 1);
                 p.slots[p.row_off[i] + q] = static_cast<int>(j);
             }
@@ -565,11 +653,12 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
 
     // --- r = y - A x_hat and ||r||_0 (done above in the local start)
     if (!local_init) {
+        const SolveState st0 = state_of(p, 0);
         int wnz = 0;
         for (int64_t i = gtid; i < p.m; i += gsize) {
-            const double ri = p.x_init ? row_residual(p, static_cast<int>(i)) : p.y[i];
+            const double ri = p.x_init ? row_residual(st0, static_cast<int>(i)) : p.y[i];
             p.r[i] = ri;
-            p.rword[i] = row_word(ri, tau, inv_w);
+            put_word<WM>(p.rword, static_cast<uint32_t>(i), row_word(ri, tau, inv_w));
             wnz += wave_count(fabs(ri) > tau);
         }
         const int b = block_sum((tid & 63) == 0 ? wnz : 0);
@@ -579,6 +668,9 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             return;
         }
         nnz = ld_relaxed(&c->nnz);
+        // every bucket word into this workgroup's LDS copy, once: after each
+        // iteration only the rows it touched are refreshed
+        if (Words<WM>::kLds) stage_words<WM>(p, lds_w);
     }
     if (gtid == 0 && p.trace) p.trace[0] = nnz;
 
@@ -593,32 +685,14 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         if (nnz == 0) { outcome = L0_CONVERGED; break; }
         if (l == p.max_iter) { outcome = L0_MAX_ITER; break; }
         const int pos = pass % D;
+        const SolveState st = state_of(p, l);
 
-        // vote on the same residual for every column (the local start left
-        // the first pass's words in LDS)
-        if (COMPACT && !(local_init && pass == 0)) {
-            // 16-byte loads (the word array is 256-byte aligned), four in
-            // flight per thread before the LDS stores: 64 KiB of words per
-            // round; the last m % 4 words one by one
-            const int m4 = p.m >> 2;
-            const uint4* src4 = reinterpret_cast<const uint4*>(p.rword);
-            uint4* dst4 = reinterpret_cast<uint4*>(lds_w);
-            int i = tid;
-            for (; i + 3 * kBlock < m4; i += 4 * kBlock) {
-                const uint4 a0 = src4[i], a1 = src4[i + kBlock];
-                const uint4 a2 = src4[i + 2 * kBlock], a3 = src4[i + 3 * kBlock];
-                dst4[i] = a0;
-                dst4[i + kBlock] = a1;
-                dst4[i + 2 * kBlock] = a2;
-                dst4[i + 3 * kBlock] = a3;
-            }
-            for (; i < m4; i += kBlock) dst4[i] = src4[i];
-            for (int t = (m4 << 2) + tid; t < p.m; t += kBlock) lds_w[t] = p.rword[t];
-            __syncthreads();
-        }
+        // vote on the same residual for every column (the LDS copy of the
+        // words is current: staged at the start, refreshed after each
+        // iteration)
         if (p.timeline && site.member == 0 && tid == 0)
             p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
-        vote_phase<D, COMPACT>(p, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member, site.count);
+        vote_phase<D, WM>(p, st, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member, site.count);
         if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
             return;
@@ -633,18 +707,18 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         empty = 0;
 
         // residual update of the touched rows, ||r||_0 by its change
+        const int na = ld_relaxed(&p.affc[l]);
         {
-            const int na = ld_relaxed(&p.affc[l]);
             // Each pass of this grid-stride loop has lane 0 of the wave active
             // whenever any lane is, so lane 0 accumulates the wave's change.
             int wdelta = 0;
             for (int64_t q = gtid; q < na; q += gsize) {
-                const int i = p.aff_list[q];
-                const double rn = row_residual(p, i);
+                const int i = st.aff_list[q];
+                const double rn = row_residual(st, i);
                 const bool was = fabs(p.r[i]) > tau;
                 const bool now = fabs(rn) > tau;
                 p.r[i] = rn;
-                p.rword[i] = row_word(rn, tau, inv_w);
+                put_word<WM>(p.rword, static_cast<uint32_t>(i), row_word(rn, tau, inv_w));
                 p.aff_flag[i] = 0;
                 wdelta += wave_count(now && !was) - wave_count(was && !now);
             }
@@ -657,6 +731,19 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         }
         nnz = ld_relaxed(&c->nnz);
         updates += tc;
+        // refresh this workgroup's LDS words of the rows the iteration
+        // touched (the list of this iteration's parity: the next iteration
+        // appends to the other one)
+        if (Words<WM>::kLds) {
+            using T = typename Words<WM>::T;
+            T* lw = reinterpret_cast<T*>(lds_w);
+            const T* gw = static_cast<const T*>(p.rword);
+            for (int q = tid; q < na; q += kBlock) {
+                const int i = st.aff_list[q];
+                lw[i] = gw[i];
+            }
+            __syncthreads();
+        }
         ++l;
         if (gtid == 0) {
             if (p.trace) p.trace[l] = nnz;
@@ -898,7 +985,7 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s,
     const size_t stage_bytes = static_cast<size_t>(kRepackWaves) * 64 * D * sizeof(int);
     const int lds_hist = hist_bytes + stage_bytes <= kLdsWordBytes ? 1 : 0;
     const size_t lds = (lds_hist ? hist_bytes : 0) + stage_bytes;
-    const void* fn = A.compact ? (lds_hist ? reinterpret_cast<const void*>(&repack_kernel<D, uint16_t, true>)
+    const void* fn = A.rows16 ? (lds_hist ? reinterpret_cast<const void*>(&repack_kernel<D, uint16_t, true>)
                                            : reinterpret_cast<const void*>(&repack_kernel<D, uint16_t, false>))
                                : (lds_hist ? reinterpret_cast<const void*>(&repack_kernel<D, int32_t, true>)
                                            : reinterpret_cast<const void*>(&repack_kernel<D, int32_t, false>));
@@ -918,10 +1005,11 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s,
     return hipGetLastError();
 }
 
-template <int D, bool COMPACT>
+template <int D, int WM>
 hipError_t solve_d(const SolveParams& p, hipStream_t s) {
-    const void* fn = reinterpret_cast<const void*>(&solve_kernel<D, COMPACT>);
-    const size_t lds = COMPACT ? static_cast<size_t>(p.m) * sizeof(uint32_t) : 0;
+    const void* fn = reinterpret_cast<const void*>(&solve_kernel<D, WM>);
+    // the LDS word copy, rounded up for the 16-byte staging copies
+    const size_t lds = WM == kWordsGlobal ? 0 : (static_cast<size_t>(p.m) * word_bytes(WM) + 15) / 16 * 16;
     hipError_t e;
     if (lds > 64 * 1024) {
         e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
@@ -967,8 +1055,12 @@ hipError_t solve_d(const SolveParams& p, hipStream_t s) {
 
 template <int D>
 hipError_t solve_dispatch_r(const SolveParams& p, hipStream_t s) {
-    if (p.compact) return solve_d<D, true>(p, s);
-    return solve_d<D, false>(p, s);
+    switch (p.wmode) {
+        case kWordsLds32: return solve_d<D, kWordsLds32>(p, s);
+        case kWordsLds16: return solve_d<D, kWordsLds16>(p, s);
+        case kWordsLds8: return solve_d<D, kWordsLds8>(p, s);
+        default: return solve_d<D, kWordsGlobal>(p, s);
+    }
 }
 
 template <int D = kDMin>

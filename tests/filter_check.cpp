@@ -3,8 +3,8 @@
 //  2. bucket_filter<D> equals its definition on random words;
 //  3. exact_score<D> equals the l0-decrease eq. (selection_l0) formed entry
 //     by entry, best score first and smallest value on ties;
-//  4. the filter (on 32-bit words, and on words folded to 16 bits) never
-//     rejects a column exact_score selects, on adversarial
+//  4. the filter (on 32-bit words, and on words folded to 16 and to 8 bits)
+//     never rejects a column exact_score selects, on adversarial
 //     columns (clusters within tau, zeros, tiny values, values straddling
 //     bucket edges) for several tau, both rules and every threshold.
 // Exit status 0 and "OK" on success.
@@ -66,7 +66,7 @@ template <int D>
 static int check_exactness(int trials) {
     const double ymax = 3.0;
     const double taus[] = {0.0, 1e-10 * ymax, 1e-6 * ymax, 1e-3 * ymax, 0x1p-40, 0.37};
-    long selected = 0, passed = 0, folded_passed = 0;
+    long selected = 0, passed = 0, folded_passed = 0, folded8_passed = 0;
     for (double tau : taus) {
         const double width = bucket_width(tau, ymax);
         const double inv_w = 1.0 / width;
@@ -140,6 +140,22 @@ static int check_exactness(int trials) {
                                     rule);
                         return 1;
                     }
+                    // 8-bit folds (of the 32-bit words): a word holding
+                    // bucket bit k holds 8-bit bit (k mod 7) too, so they
+                    // pass what the 32-bit words pass
+                    uint32_t w8[D];
+                    for (int t = 0; t < D; ++t) {
+                        w8[t] = unfold_word8(fold_word8(w[t]));
+                        if ((w8[t] >> 31) != (w[t] >> 31)) { std::printf("fold8 lost the zero flag\n"); return 1; }
+                        if ((w8[t] & 0x7FFFFF80u) != 0u) { std::printf("fold8 left high bucket bits\n"); return 1; }
+                    }
+                    const bool f8pass = bucket_filter<D>(w8, a, rule);
+                    folded8_passed += f8pass;
+                    if (pass && !f8pass) {
+                        std::printf("8-BIT FOLDED FILTER REJECTED A PASSING COLUMN D=%d tau=%g a=%d rule=%d\n", D,
+                                    tau, a, rule);
+                        return 1;
+                    }
                     // shifted rule (Algorithm 3): candidate v[t] only, by its
                     // definition; the filter (with the shifted rule's zero
                     // term) must pass every column it selects
@@ -162,7 +178,8 @@ static int check_exactness(int trials) {
                             std::printf("exact_score_shifted D=%d t=%d mismatch\n", D, t);
                             return 1;
                         }
-                        if (ssel && (!bucket_filter<D>(w, a, srule) || !bucket_filter<D>(wf, a, srule))) {
+                        if (ssel && (!bucket_filter<D>(w, a, srule) || !bucket_filter<D>(wf, a, srule) ||
+                                     !bucket_filter<D>(w8, a, srule))) {
                             std::printf("FILTER REJECTED A SHIFTED SELECTION D=%d tau=%g a=%d rule=%d\n", D, tau, a,
                                         srule);
                             return 1;
@@ -171,7 +188,8 @@ static int check_exactness(int trials) {
                 }
         }
     }
-    std::printf("D=%d selected=%ld passed=%ld passed with folded words=%ld\n", D, selected, passed, folded_passed);
+    std::printf("D=%d selected=%ld passed=%ld passed with 16-bit folded words=%ld, 8-bit=%ld\n", D, selected, passed,
+                folded_passed, folded8_passed);
     return 0;
 }
 

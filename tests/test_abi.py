@@ -37,10 +37,13 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_workspace_bytes_host_only():
-    # at least the repacked index store (16-bit rows for m <= 36864, else
+    # at least the repacked index store (16-bit rows for m <= 65536, else
     # 32-bit) plus the per-row support lists (one int32 per edge)
     assert l0.l0_workspace_bytes(4096, 512, 7, 100) >= 4096 * 7 * (2 + 4)
-    assert l0.l0_workspace_bytes(4096, 40000, 7, 100) >= 4096 * 7 * (4 + 4)
+    assert l0.l0_workspace_bytes(4096, 65536, 7, 100) >= 4096 * 7 * (2 + 4)
+    assert l0.l0_workspace_bytes(4096, 65537, 7, 100) >= 4096 * 7 * (4 + 4)
+    assert (l0.l0_workspace_bytes(4096, 65537, 7, 100) - l0.l0_workspace_bytes(4096, 65536, 7, 100)
+            >= 4096 * 7 * 2)
     # invalid shapes give 0
     for args in [(0, 512, 7, 10), (4096, 0, 7, 10), (4096, 512, 1, 10), (4096, 512, 21, 10),
                  (10, 5, 7, 10), (4096, 512, 7, -1), (1 << 31, 512, 7, 10)]:

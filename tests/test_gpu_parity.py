@@ -82,10 +82,15 @@ def test_shapes_shifted(n, m, d, k):
 @pytest.mark.parametrize("n,m,d,k", [
     (100003, 10007, 7, 700),    # many tiles, ragged tail, r in LDS
     (100003, 10007, 7, 2500),   # stalls (dense for alpha = 4)
-    (262144, 26215, 7, 2621),   # 16-bit rows, bucket words in LDS
-    (400000, 40000, 7, 3000),   # m too large for LDS: 32-bit rows, words from L2
-    (300000, 36864, 9, 2000),   # largest m with words in LDS
-    (300000, 36865, 5, 2000),   # smallest m without
+    (262144, 26215, 7, 2621),   # 16-bit rows, 32-bit bucket words in LDS
+    (300000, 36864, 9, 2000),   # largest m with 32-bit words in LDS
+    (300000, 36865, 5, 2000),   # smallest m with 16-bit folded words in LDS
+    (400000, 40000, 7, 3000),   # 16-bit folded words
+    (300000, 65536, 7, 2500),   # largest m with 16-bit rows and words
+    (300000, 65537, 7, 2500),   # smallest m with 32-bit rows, 8-bit folded words
+    (400000, 147456, 5, 4000),  # largest m with 8-bit words in LDS
+    (400000, 147457, 5, 4000),  # smallest m with words gathered from global memory
+    (600000, 400000, 7, 9000),  # global words
     (50000, 5000, 5, 400),
     (50000, 5000, 9, 300),
     (30000, 3000, 3, 150),
