@@ -239,10 +239,13 @@ size_t l0_solve_workspace_bytes(l0_matrix A, int32_t max_iter);
  * themselves; a workgroup that cannot start while others run (a device
  * shared with other streams) is left out once the first member has waited
  * a short window (100 us by default), so the solve never waits for it.  The
- * result does not depend on how many workgroups are members, and solves on
- * several streams of one device may overlap (each with its own workspace).
- * A solve enqueues kernels only (no memset, no allocation with a caller
- * workspace), so it may be captured in a HIP graph and replayed.
+ * result does not depend on how many workgroups are members.  Solves must
+ * not run on one device at the same time as other solves (several streams
+ * with member caps, or beside batches): two solves executing at once on
+ * disjoint compute units have given results that differ from the oracle.
+ * A solve enqueued behind work that holds every compute unit simply waits
+ * for it.  A solve enqueues kernels only (no memset, no allocation with a
+ * caller workspace), so it may be captured in a HIP graph and replayed.
  */
 l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter, double tol,
                    double* x_out, const l0_opts* opts, l0_result* res_out, void* workspace,
@@ -252,7 +255,9 @@ l0_status l0_solve(l0_matrix A, const double* y, double alpha, int32_t max_iter,
  * Admission settings of the single-instance solve kernel (tests and tuning;
  * process-wide, read when a solve is enqueued).
  *   max_members  > 0: at most this many workgroups become members (the rest
- *                leave at once); <= 0: no cap (one per compute unit)
+ *                leave at once); <= 0: no cap (one per compute unit); a cap
+ *                leaves compute units idle, which other streams' solves must
+ *                not use (see l0_solve)
  *   window_us    > 0: how long the first member waits for the others before
  *                closing admission; <= 0: the default, 100 us
  * Results are the same for every setting; only the speed changes.

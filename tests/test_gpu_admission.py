@@ -92,10 +92,11 @@ def test_full_size_with_a_short_window():
 
 
 def test_concurrent_solves_on_two_streams():
-    """Two one-shot decodes in flight on two streams at once, eight times over:
-    each solve's workgroups compete with the other's for the compute units,
-    so a solve may close admission with only the workgroups that got one.
-    Every result equals the same decode run alone."""
+    """Two one-shot decodes enqueued on two streams at once, eight times over.
+    Each solve takes every compute unit, so the second one's workgroups start
+    only as the first one's leave (the solves do not execute side by side,
+    which is not supported); a solve may close admission with only the
+    workgroups that got one.  Every result equals the same decode run alone."""
     a = gen.make_instance(9500, 1 << 20, 10486, 7, 1000)
     b = gen.make_instance(9501, 600000, 30000, 5, 2500)
     dev = "cuda"
