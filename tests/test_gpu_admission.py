@@ -98,7 +98,7 @@ def test_concurrent_solves_on_two_streams():
     which is not supported); a solve may close admission with only the
     workgroups that got one.  Every result equals the same decode run alone."""
     a = gen.make_instance(9500, 1 << 20, 10486, 7, 1000)
-    b = gen.make_instance(9501, 600000, 30000, 5, 2500)
+    b = gen.make_instance(9501, 1 << 20, 30000, 5, 2500)  # 4096 tiles: a grid of one workgroup per CU
     dev = "cuda"
 
     def upload(i):
