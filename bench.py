@@ -687,19 +687,25 @@ def serve(args):
 
 
 # name -> (d, alpha, rule, values, scaled columns, band): the paper's protocol at its experimental
-# alpha = 2 with Algorithm 2's score, the frequency rule (parallel-LDDSR), the workloads' alpha =
-# ceil(d/2), the shifted rule, banded signals, other degrees, and +-1 signals on unit and on
-# column-scaled A.
+# alpha = 2 with Algorithm 2's score; the frequency rule at alpha = 2 and at alpha = d/2 (the
+# latter is parallel-LDDSR as Section 4.3.2 defines it, the frequency score with epsilon = 1/4,
+# i.e. alpha = (1 - 2 epsilon) d); the workloads' alpha = ceil(d/2); the shifted rule; banded
+# signals (Section 5.6); the odd degrees 5 to 19 (Section 5.7); and +-1 signals on unit and on
+# column-scaled A (Section 4.3.3).
 PHASE_CURVES = {
     "l0dec-a2": (7, 2.0, "L0DEC", "normal", False, 0.0),
     "mode-a2": (7, 2.0, "MODE", "normal", False, 0.0),
+    "lddsr-ad2": (7, 3.5, "MODE", "normal", False, 0.0),
     "l0dec-a4": (7, 4.0, "L0DEC", "normal", False, 0.0),
     "shifted-a2": (7, 2.0, "SHIFTED_L0DEC", "normal", False, 0.0),
     "band0.5-a2": (7, 2.0, "L0DEC", "normal", False, 0.5),
     "band0.9-a2": (7, 2.0, "L0DEC", "normal", False, 0.9),
     "d5-a2": (5, 2.0, "L0DEC", "normal", False, 0.0),
     "d9-a2": (9, 2.0, "L0DEC", "normal", False, 0.0),
+    "d11-a2": (11, 2.0, "L0DEC", "normal", False, 0.0),
     "d13-a2": (13, 2.0, "L0DEC", "normal", False, 0.0),
+    "d15-a2": (15, 2.0, "L0DEC", "normal", False, 0.0),
+    "d17-a2": (17, 2.0, "L0DEC", "normal", False, 0.0),
     "d19-a2": (19, 2.0, "L0DEC", "normal", False, 0.0),
     "pm1-a2": (7, 2.0, "L0DEC", "pm1", False, 0.0),
     "pm1-scaled-a2": (7, 2.0, "L0DEC", "pm1", True, 0.0),
