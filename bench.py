@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--phase-out", default="", help="phase: also write a markdown summary here")
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: server workspace budget")
+    ap.add_argument("--serve-inflight", type=int, default=4, help="serve: server batches in flight (1..4)")
+    ap.add_argument("--serve-loads", default="0.5,0.9,1.5", help="serve: loads as fractions of plain capacity")
     ap.add_argument("--sweep-count", type=int, default=4096)
     ap.add_argument("--autotune", action="store_true", help="sweep: pick the schedule with "
                     "l0_batch_autotune first")
@@ -608,7 +610,7 @@ def serve(args):
 
     rng = np.random.Generator(np.random.PCG64(gen.SEED + 4500))
     runs = []
-    for factor in (0.5, 0.9, 1.5):
+    for factor in [float(v) for v in args.serve_loads.split(",")]:
         lam = factor * capacity
         arrivals = np.cumsum(rng.exponential(1.0 / lam, count))
         # plain path: FIFO, one request at a time, starting when it has arrived
@@ -625,7 +627,7 @@ def serve(args):
         for r in reqs:
             r["x"].zero_()
         torch.cuda.synchronize()
-        srv = l0.Server(int(args.budget_gib * (1 << 30)), max_inflight=4)
+        srv = l0.Server(int(args.budget_gib * (1 << 30)), max_inflight=args.serve_inflight)
         lat_srv = [None] * count
         nsub = 0
         start = time.perf_counter()
@@ -678,7 +680,7 @@ def serve(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{count} requests, n=round(2^U) U~U[12,22], delta in {{0.01,0.1}}, d=7, "
                                "k=floor(0.15m), 10% +-1 nonzeros, Poisson arrivals at 0.5/0.9/1.5 x the plain "
-                               "path's capacity", "budget_gib": args.budget_gib, "max_inflight": 4},
+                               "path's capacity", "budget_gib": args.budget_gib, "max_inflight": args.serve_inflight},
         "roofline": None,
         "cpu_baseline": cpu,
         "detail": {"plain_capacity_per_s": round(capacity, 1), "runs": runs},
