@@ -25,7 +25,9 @@ MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d) {
     b.row_off = align256((static_cast<size_t>(m) + 1) * sizeof(int32_t));
     b.deg = align256(static_cast<size_t>(m) * sizeof(int32_t));
     b.flag = 256;
-    b.total = b.soa + b.row_off + b.deg + b.flag;
+    b.partial = repack_lds_hist(m, d) ? 0
+                                      : align256(static_cast<size_t>(deg_slices(n, d)) * m * sizeof(int32_t));
+    b.total = b.soa + b.row_off + b.deg + b.flag + b.partial;
     return b;
 }
 
@@ -115,7 +117,9 @@ l0::MatrixView carve_matrix(char* base, int64_t n, int32_t m, int32_t d) {
     v.soa = p;                                    p += b.soa;
     v.row_off = reinterpret_cast<int32_t*>(p);   p += b.row_off;
     v.deg = reinterpret_cast<int32_t*>(p);       p += b.deg;
-    v.bad_input = reinterpret_cast<int32_t*>(p);
+    v.bad_input = reinterpret_cast<int32_t*>(p); p += b.flag;
+    v.partial = b.partial ? reinterpret_cast<int32_t*>(p) : nullptr;
+    v.slices = b.partial ? l0::deg_slices(n, d) : 0;
     return v;
 }
 

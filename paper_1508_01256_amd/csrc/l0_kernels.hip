@@ -773,7 +773,6 @@ __global__ void zero_ints(int32_t* p, int64_t count) {
 // first, so enough reads are in flight to stream at HBM rate; groups that lie
 // wholly inside the array are read from one base address (immediate offsets,
 // few address registers), only the last, partial one index by index.
-constexpr int kRepackWaves = 16;
 template <int D>
 struct RepackGroups {
     static constexpr int value = D >= 28 ? 1 : 28 / D;
@@ -824,10 +823,7 @@ __global__ void __launch_bounds__(1024) repack_kernel(const int32_t* col_idx, Ma
                 const bool inside = e0 + k * 64 < nd;
                 const bool ok = static_cast<unsigned>(row) < m;
                 if (inside && !ok) bad |= kErrBadIndex;
-                if (inside && ok) {
-                    if (LDS_HIST) atomicAdd(&hist[row], 1);
-                    else atomicAdd(&A.deg[row], 1);
-                }
+                if (LDS_HIST && inside && ok) atomicAdd(&hist[row], 1);
                 stage[k * 64 + lane] = inside && ok ? row : 0;
             }
             // the wave's LDS stores complete (lgkmcnt(0)) before any lane reads
@@ -860,6 +856,51 @@ __global__ void __launch_bounds__(1024) repack_kernel(const int32_t* col_idx, Ma
         for (int i = threadIdx.x; i < A.m; i += blockDim.x)
             if (hist[i]) atomicAdd(&A.deg[i], hist[i]);
     }
+}
+
+// Partial degree counts (matrices whose m counts do not fit in the repack
+// kernel's LDS): workgroup s counts the rows of its slice of the flat index
+// array in LDS, kDegRange rows per pass (the slice is read once per pass,
+// mostly from L2 after the first), and stores the counts densely at
+// partial[s*m + row].  Indices outside [0, m) are skipped (the repack flags
+// them).
+__global__ void __launch_bounds__(1024) deg_partial_kernel(const int32_t* col_idx, MatrixView A, int64_t nd) {
+    extern __shared__ int hist[];
+    constexpr int U = 16;  // independent loads in flight per thread
+    const int tid = threadIdx.x;
+    const int64_t lo_e = nd * blockIdx.x / gridDim.x, hi_e = nd * (blockIdx.x + 1) / gridDim.x;
+    int32_t* part = A.partial + static_cast<int64_t>(blockIdx.x) * A.m;
+    for (int r0 = 0; r0 < A.m; r0 += kDegRange) {
+        const int len = min(kDegRange, A.m - r0);
+        for (int i = tid; i < len; i += 1024) hist[i] = 0;
+        __syncthreads();
+        for (int64_t base = lo_e; base < hi_e; base += int64_t(1024) * U) {
+            int v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t e = base + static_cast<int64_t>(u) * 1024 + tid;
+                v[u] = col_idx[e < hi_e ? e : hi_e - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t e = base + static_cast<int64_t>(u) * 1024 + tid;
+                const unsigned rel = static_cast<unsigned>(v[u] - r0);
+                if (e < hi_e && rel < static_cast<unsigned>(len)) atomicAdd(&hist[rel], 1);
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < len; i += 1024) part[r0 + i] = hist[i];
+        __syncthreads();
+    }
+}
+
+// deg[i] = sum over the slices of partial[s*m + i].
+__global__ void __launch_bounds__(256) deg_reduce_kernel(MatrixView A) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.m) return;
+    int s = 0;
+    for (int k = 0; k < A.slices; ++k) s += A.partial[static_cast<int64_t>(k) * A.m + i];
+    A.deg[i] = s;
 }
 
 // row_off = exclusive prefix sum of the row degrees (one workgroup), chunk by
@@ -983,7 +1024,8 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s,
     }
     const size_t hist_bytes = static_cast<size_t>(A.m) * sizeof(int);
     const size_t stage_bytes = static_cast<size_t>(kRepackWaves) * 64 * D * sizeof(int);
-    const int lds_hist = hist_bytes + stage_bytes <= kLdsWordBytes ? 1 : 0;
+    const int lds_hist = repack_lds_hist(A.m, D) ? 1 : 0;
+    if (!lds_hist && !A.partial) return hipErrorInvalidValue;  // the layout has no partial counts
     const size_t lds = (lds_hist ? hist_bytes : 0) + stage_bytes;
     const void* fn = A.rows16 ? (lds_hist ? reinterpret_cast<const void*>(&repack_kernel<D, uint16_t, true>)
                                            : reinterpret_cast<const void*>(&repack_kernel<D, uint16_t, false>))
@@ -1001,6 +1043,17 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s,
     void* args[] = {const_cast<int32_t**>(&col_idx), const_cast<MatrixView*>(&A)};
     hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(blocks)), dim3(1024), args, lds, s);
     if (e != hipSuccess) return e;
+    if (!lds_hist) {
+        const void* pf = reinterpret_cast<const void*>(&deg_partial_kernel);
+        const size_t plds = static_cast<size_t>(kDegRange) * sizeof(int);
+        e = hipFuncSetAttribute(pf, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(plds));
+        if (e != hipSuccess) return e;
+        int64_t nd = A.n * D;
+        void* pargs[] = {const_cast<int32_t**>(&col_idx), const_cast<MatrixView*>(&A), &nd};
+        e = hipLaunchKernel(pf, dim3(static_cast<unsigned>(A.slices)), dim3(1024), pargs, plds, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(deg_reduce_kernel, dim3(static_cast<unsigned>((A.m + 255) / 256)), dim3(256), 0, s, A);
+    }
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, A, clear.p, clear.count);
     return hipGetLastError();
 }
