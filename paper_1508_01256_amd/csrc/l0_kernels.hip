@@ -387,11 +387,42 @@ __device__ __forceinline__ void filter_chunk(const SolveParams& p, const void* w
     }
 }
 
+// x_hat of chunk g's columns to zero (the first vote of a solve from x_hat =
+// 0 clears x_hat this way, beside the index loads).  x is 16-byte aligned
+// and g uniform over the wave.  The streaming store is a raw buffer store
+// over the chunk's columns below n: lanes past the end are dropped by the
+// buffer's range check, so every call issues exactly one store and the
+// waits for the index loads can count it.  With 16-bit rows a lane clears a
+// pair of columns; the range covers whole pairs (the last column of an odd
+// n is cleared apart, see vote_phase).  A chunk at or past n stores nothing.
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit dwords (gfx9)
+constexpr int kStoreNt = 2;             // streaming (nt) store
+
+template <bool R16>
+__device__ __forceinline__ void clear_chunk_x(double* x, uint32_t g, uint32_t n, uint32_t lane) {
+    constexpr uint32_t kCols = Chunk<R16>::kCols;
+    const uint32_t j0 = g * kCols;
+    uint32_t cols = j0 < n ? min(kCols, n - j0) : 0u;
+    if constexpr (R16) cols &= ~1u;
+    const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(x + (j0 < n ? j0 : 0u), 0, static_cast<int>(cols * 8),
+                                                        kRsrcWord3);
+    if constexpr (R16) {
+        typedef int int4v __attribute__((ext_vector_type(4)));
+        const int4v z = {0, 0, 0, 0};
+        __builtin_amdgcn_raw_buffer_store_b128(z, rsrc, static_cast<int>(lane * 16), 0, kStoreNt);
+    } else {
+        typedef int int2v __attribute__((ext_vector_type(2)));
+        const int2v z = {0, 0};
+        __builtin_amdgcn_raw_buffer_store_b64(z, rsrc, static_cast<int>(lane * 8), 0, kStoreNt);
+    }
+}
+
 // Vote phase.  Each wave streams its chunks (g = wave, wave + stride, ...)
 // with two chunks' row indices in flight (two register buffers taking turns,
 // so no copy waits on a load), gathers the rows' bucket words and runs the
-// bucket filter; the loop issues no global store, so its waits cover loads
-// only.  Columns passing the filter are then scored exactly on the same
+// bucket filter.  Its only global stores are the first vote's x_hat clears,
+// each issued after the loads that the next wait covers, so every wait
+// still covers loads only.  Columns passing the filter are then scored exactly on the same
 // residual.  If the workgroup's queue overflowed, the queue is dropped and
 // the workgroup filters its chunks again, scoring each passing column at
 // once (slow, but only for inputs where the filter passes thousands of
@@ -399,8 +430,10 @@ __device__ __forceinline__ void filter_chunk(const SolveParams& p, const void* w
 // through atomic counters costs more than the imbalance it removes (a wave
 // cannot wait for a chunk's loads without also waiting for an older claim).
 // l: the iteration (update counters); pos: the position shifted rules try in
-// this pass.
-template <int D, int WM>
+// this pass; clear_x: also zero x_hat chunk by chunk (each column's x_hat is
+// then zero before its workgroup scores it: the clears are complete before
+// the workgroup barrier that precedes the scoring).
+template <int D, int WM, bool CLEAR>
 __device__ void vote_phase(const SolveParams& p, const SolveState& st, int l, double tau, const void* lds_w,
                            int* q_items, int* q_count, int* q_ovf, int pos, unsigned member, unsigned members) {
     constexpr bool R16 = Words<WM>::kRows16;
@@ -408,23 +441,54 @@ __device__ void vote_phase(const SolveParams& p, const SolveState& st, int l, do
     const uint32_t nchunks = static_cast<uint32_t>(p.ntiles) * Chunk<R16>::kPerTile;
     const uint32_t n = static_cast<uint32_t>(p.n);
     const void* words = Words<WM>::kLds ? lds_w : p.rword;
-    const uint32_t stride = members * kWaves;
-    const uint32_t first = member * kWaves + (threadIdx.x >> 6);
+    // chunk numbers are uniform over the wave (scalar registers)
+    const uint32_t stride = __builtin_amdgcn_readfirstlane(members * kWaves);
+    const uint32_t first = __builtin_amdgcn_readfirstlane(member * kWaves + (threadIdx.x >> 6));
     // prefetches past the last chunk read the last chunk again (an L2 hit;
     // unconditional loads keep the waits exact)
     const uint32_t last = nchunks - 1;
     uint32_t g = first;
     uint32_t a[D], b[D];
-    load_chunk<D, R16>(p.soa, min(g, last), lane, a);
-    load_chunk<D, R16>(p.soa, min(g + stride, last), lane, b);
-    while (g < nchunks) {
-        filter_chunk<D, WM>(p, words, a, g, n, lane, q_items, q_count, q_ovf);
-        load_chunk<D, R16>(p.soa, min(g + 2 * stride, last), lane, a);
-        g += stride;
-        if (g >= nchunks) break;
-        filter_chunk<D, WM>(p, words, b, g, n, lane, q_items, q_count, q_ovf);
-        load_chunk<D, R16>(p.soa, min(g + 2 * stride, last), lane, b);
-        g += stride;
+    if constexpr (!CLEAR) {
+        load_chunk<D, R16>(p.soa, min(g, last), lane, a);
+        load_chunk<D, R16>(p.soa, min(g + stride, last), lane, b);
+        while (g < nchunks) {
+            filter_chunk<D, WM>(p, words, a, g, n, lane, q_items, q_count, q_ovf);
+            load_chunk<D, R16>(p.soa, min(g + 2 * stride, last), lane, a);
+            g += stride;
+            if (g >= nchunks) break;
+            filter_chunk<D, WM>(p, words, b, g, n, lane, q_items, q_count, q_ovf);
+            load_chunk<D, R16>(p.soa, min(g + 2 * stride, last), lane, b);
+            g += stride;
+        }
+    } else {
+        // The same stream with a clear after each chunk, in whole pairs of
+        // chunks (a pair's second chunk past the end filters columns >= n,
+        // which never pass, and clears nothing): with no exit between the
+        // two halves every wait follows one fixed issue order, loads of one
+        // buffer, a store, loads of the other, and counts the store exactly
+        // (the store to nothing between the first loads of a and b keeps
+        // the first pass in that order).
+        load_chunk<D, R16>(p.soa, min(g, last), lane, a);
+        clear_chunk_x<R16>(p.x, nchunks, n, lane);
+        load_chunk<D, R16>(p.soa, min(g + stride, last), lane, b);
+        while (g < nchunks) {
+            filter_chunk<D, WM>(p, words, a, g, n, lane, q_items, q_count, q_ovf);
+            clear_chunk_x<R16>(p.x, g, n, lane);
+            load_chunk<D, R16>(p.soa, min(g + 2 * stride, last), lane, a);
+            filter_chunk<D, WM>(p, words, b, g + stride, n, lane, q_items, q_count, q_ovf);
+            clear_chunk_x<R16>(p.x, g + stride, n, lane);
+            load_chunk<D, R16>(p.soa, min(g + 3 * stride, last), lane, b);
+            g += 2 * stride;
+        }
+        if constexpr (R16) {
+            // the last column of an odd n, by the wave owning its chunk
+            const uint32_t cl = (n - 1) / Chunk<true>::kCols;
+            if ((n & 1) && cl >= first && (cl - first) % stride == 0 && lane == 0) p.x[n - 1] = 0.0;
+        }
+        // the clears are done (written to L2) before any wave of the
+        // workgroup scores a column, which reads and writes its x_hat
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     }
     __syncthreads();
     if (p.timeline && member == 0 && threadIdx.x == 0)
@@ -487,6 +551,11 @@ __device__ void stage_words(const SolveParams& p, void* lds_w) {
 // the persistent solve kernel
 // ---------------------------------------------------------------------------
 
+// x_hat = 0 over the grid (a solve from zero that ends before its first vote).
+__device__ void zero_x(const SolveParams& p, int64_t gtid, int64_t gsize) {
+    for (int64_t j = gtid; j < p.n; j += gsize) p.x[j] = 0.0;
+}
+
 // Waves per SIMD the compiler must allow: one resident workgroup per CU (4
 // waves), which leaves 128 VGPRs per lane (no spills).  Two workgroups per CU
 // (8 waves, 64 VGPRs) were measured slower: the second workgroup on a CU
@@ -527,8 +596,6 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     // nothing.
     const bool local_init = WM == kWordsLds32 && p.x_init == nullptr;
 
-    // (The local start reads y before the init below floods the memory
-    // system with the stores that clear x_hat.)
     double ymax = 0.0;
     int nnz = 0;
     if (local_init) {
@@ -571,21 +638,16 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         for (int64_t i = gtid; i < p.m; i += gsize) static_cast<uint32_t*>(p.rword)[i] = lds_w[i];
         if (gtid == 0) __hip_atomic_store(&c->nnz, nnz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    // --- init: x_hat, support bitmap, per-row state, max |y|, finiteness of
-    //     y, usable column weights
+    // --- init: x_hat (a resume copies x_init; from zero, the first vote
+    //     clears a 16-byte aligned x_hat as it streams the index store),
+    //     support bitmap, per-row state, max |y|, finiteness of y, usable
+    //     column weights
+    const bool fuse_clear = p.x_init == nullptr && (reinterpret_cast<uintptr_t>(p.x) & 15) == 0;
     {
         int bad_w = 0;
         if (p.x_init) {
             for (int64_t j = gtid; j < p.n; j += gsize) p.x[j] = p.x_init[j];
-        } else if ((reinterpret_cast<uintptr_t>(p.x) & 15) == 0) {
-            // streaming 16-byte stores: x_hat is not read again before the
-            // scores of the first vote touch a few of its entries
-            typedef double dbl2 __attribute__((ext_vector_type(2)));
-            dbl2* x2 = reinterpret_cast<dbl2*>(p.x);
-            const dbl2 z = {0.0, 0.0};
-            for (int64_t j = gtid; j < (p.n >> 1); j += gsize) __builtin_nontemporal_store(z, &x2[j]);
-            if (gtid == 0 && (p.n & 1)) p.x[p.n - 1] = 0.0;
-        } else {
+        } else if (!fuse_clear) {
             for (int64_t j = gtid; j < p.n; j += gsize) p.x[j] = 0.0;
         }
         if (p.w)
@@ -624,6 +686,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     }
     const int err = ld_relaxed(&c->err);
     if (err) {
+        if (fuse_clear) zero_x(p, gtid, gsize);
         if (gtid == 0) write_result(p, 0, error_outcome(err), 0, 0, 0);
         return;
     }
@@ -682,8 +745,12 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     int outcome;
     long long updates = 0;
     for (;;) {
-        if (nnz == 0) { outcome = L0_CONVERGED; break; }
-        if (l == p.max_iter) { outcome = L0_MAX_ITER; break; }
+        if (nnz == 0 || l == p.max_iter) {
+            // ended before any vote: x_hat (from zero) was not cleared yet
+            if (pass == 0 && fuse_clear) zero_x(p, gtid, gsize);
+            outcome = nnz == 0 ? L0_CONVERGED : L0_MAX_ITER;
+            break;
+        }
         const int pos = pass % D;
         const SolveState st = state_of(p, l);
 
@@ -692,7 +759,11 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         // iteration)
         if (p.timeline && site.member == 0 && tid == 0)
             p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
-        vote_phase<D, WM>(p, st, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member, site.count);
+        if (pass == 0 && fuse_clear)
+            vote_phase<D, WM, true>(p, st, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member, site.count);
+        else
+            vote_phase<D, WM, false>(p, st, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member,
+                                     site.count);
         if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
             return;
