@@ -80,72 +80,89 @@ struct Admission {
     unsigned cap;     // at most this many members
 };
 
-// Start-up.  Every workgroup registers on the admission word and takes the
-// registration number as its member id; ids below min(grid, cap) are
-// members, and a member records its XCD at once (during the launch ramp).
-// The member that completes the count publishes it.  If some workgroups
-// cannot start (the device is shared), the first member closes admission
-// `window` ticks after it started: the members are then the workgroups
-// registered by that time, and any later one finds admission closed and
-// leaves at once.  The members wait (relaxed) until all of them have
-// recorded their XCDs; every count is final afterwards.  Returns 1 for a
-// member, 0 for a workgroup turned away (it must leave without touching
-// anything), -1 when a wait timed out.  With a timeline, member 0 stamps its
-// start in entry 0.
-__device__ int admit(Ctrl* c, BarrierSite& b, unsigned cap, uint64_t window, uint64_t limit,
-                     int64_t* timeline) {
-    __shared__ unsigned s_site[5];
-    __shared__ int s_state;
+// Start-up, in two steps.  admit_register: every workgroup registers on the
+// admission word and takes the registration number as its member id; ids
+// below min(grid, cap) are members, and a member records its XCD at once
+// (during the launch ramp); the member that completes the count publishes
+// it.  A member may then do work that needs neither the member count nor
+// the other members (the solve's local start) before admit_complete: if
+// some workgroups cannot start (the device is shared), the first member
+// closes admission `window` ticks after it started, the members being the
+// workgroups registered by then (any later one finds admission closed and
+// leaves at once); the members wait (relaxed) until all of them have
+// recorded their XCDs, and every count is final afterwards.
+// admit_register returns 1 for a member and 0 for a workgroup turned away
+// (it must leave without touching anything); admit_complete returns 1, or
+// -1 when a wait timed out.  With a timeline, member 0 stamps its start in
+// entry 0.
+struct Registration {
+    uint64_t t0;    // start of this workgroup (thread 0)
+    unsigned want;  // min(grid, cap)
+};
+
+__device__ int admit_register(Ctrl* c, BarrierSite& b, Registration& reg, unsigned cap, int64_t* timeline) {
+    __shared__ unsigned s_reg[2];
     if (threadIdx.x == 0) {
-        const uint64_t t0 = wall_clock64();
-        const unsigned want = min(gridDim.x, cap);
+        reg.t0 = wall_clock64();
+        reg.want = min(gridDim.x, cap);
         const unsigned id = __hip_atomic_fetch_add(&c->admit, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int state = (id < want) ? 1 : 0;  // id >= kClosed > want once closed
-        unsigned count = 0, x = 0, nx = 0, nxcc = 0;
-        if (state) {
-            if (timeline && id == 0) timeline[0] = static_cast<int64_t>(t0);
+        const bool member = id < reg.want;  // id >= kClosed > want once closed
+        unsigned x = 0;
+        if (member) {
+            if (timeline && id == 0) timeline[0] = static_cast<int64_t>(reg.t0);
             x = xcc_id();
             __hip_atomic_fetch_add(&c->xcount[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the XCD count is in before the arrival
             __hip_atomic_fetch_add(&c->start, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (id + 1 == want) {
-                __hip_atomic_store(&c->members, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else if (id == 0) {
-                while (__hip_atomic_load(&c->members, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-                    if (wall_clock64() - t0 > window) {
-                        // registrations before the close are ids 0 .. v-1
-                        const unsigned v = __hip_atomic_fetch_or(&c->admit, kClosed, __ATOMIC_RELAXED,
-                                                                 __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(&c->members, min(v & (kClosed - 1u), want), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+            if (id + 1 == reg.want)
+                __hip_atomic_store(&c->members, reg.want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_reg[0] = member ? id : kClosed;
+        s_reg[1] = x;
+    }
+    __syncthreads();
+    b.member = s_reg[0];
+    b.xcc = s_reg[1];
+    b.epoch = 0;
+    return b.member != kClosed ? 1 : 0;
+}
+
+__device__ int admit_complete(Ctrl* c, BarrierSite& b, const Registration& reg, uint64_t window,
+                              uint64_t limit) {
+    __shared__ unsigned s_site[3];
+    __shared__ int s_state;
+    if (threadIdx.x == 0) {
+        if (b.member == 0 && reg.want > 1) {
+            while (__hip_atomic_load(&c->members, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                if (wall_clock64() - reg.t0 > window) {
+                    // registrations before the close are ids 0 .. v-1
+                    const unsigned v = __hip_atomic_fetch_or(&c->admit, kClosed, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&c->members, min(v & (kClosed - 1u), reg.want), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    break;
                 }
-            }
-            state = wait_at_least(&c->members, 1u, c, limit) ? 1 : -1;
-            count = __hip_atomic_load(&c->members, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (state == 1) state = wait_at_least(&c->start, count, c, limit) ? 1 : -1;
-            for (int i = 0; i < kMaxXcc; ++i) {
-                const unsigned v = __hip_atomic_load(&c->xcount[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                nxcc += v != 0;
-                if (i == static_cast<int>(x)) nx = v;
+                __builtin_amdgcn_s_sleep(1);
             }
         }
-        s_site[0] = id;
-        s_site[1] = count;
-        s_site[2] = x;
-        s_site[3] = nx;
-        s_site[4] = nxcc;
+        int state = wait_at_least(&c->members, 1u, c, limit) ? 1 : -1;
+        const unsigned count = __hip_atomic_load(&c->members, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (state == 1) state = wait_at_least(&c->start, count, c, limit) ? 1 : -1;
+        unsigned nx = 0, nxcc = 0;
+        for (int i = 0; i < kMaxXcc; ++i) {
+            const unsigned v = __hip_atomic_load(&c->xcount[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            nxcc += v != 0;
+            if (i == static_cast<int>(b.xcc)) nx = v;
+        }
+        s_site[0] = count;
+        s_site[1] = nx;
+        s_site[2] = nxcc;
         s_state = state;
     }
     __syncthreads();
-    b.member = s_site[0];
-    b.count = s_site[1];
-    b.xcc = s_site[2];
-    b.nx = s_site[3];
-    b.nxcc = s_site[4];
-    b.epoch = 0;
+    b.count = s_site[0];
+    b.nx = s_site[1];
+    b.nxcc = s_site[2];
     return s_state;
 }
 
@@ -577,23 +594,14 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     Ctrl* c = p.ctrl;
     const uint64_t limit = adm.limit;
     BarrierSite site;
-    const int state = admit(c, site, adm.cap, adm.window, limit, p.timeline);
-    if (state == 0) return;  // not admitted: the members do all the work
-    // work is split by member id over the members
-    const int64_t gtid = static_cast<int64_t>(site.member) * kBlock + tid;
-    const int64_t gsize = static_cast<int64_t>(site.count) * kBlock;
-    if (state < 0) {
-        if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
-        return;
-    }
-    if (p.timeline && site.member == 0 && tid == 0)
-        p.timeline[3 * p.max_iter + 7] = static_cast<int64_t>(wall_clock64());
+    Registration reg;
+    if (!admit_register(c, site, reg, adm.cap, p.timeline)) return;  // turned away: the members do the work
 
     // Without a resume vector and with 32-bit words in LDS (y then has at
     // most 36864 entries), every workgroup derives max |y|, tau, ||y||_0 and
-    // all bucket words of r = y from y itself: no grid barrier is needed
-    // between the start-up and the first vote, and the first pass stages
-    // nothing.
+    // all bucket words of r = y from y itself, during the launch ramp (it
+    // needs no other member): no grid barrier is needed between the
+    // start-up and the first vote, and the first pass stages nothing.
     const bool local_init = WM == kWordsLds32 && p.x_init == nullptr;
 
     double ymax = 0.0;
@@ -601,7 +609,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     if (local_init) {
         // max |y| over every row, in every workgroup (a maximum is exact in
         // any order, so all workgroups agree); non-finite y is reported by
-        // the shares above
+        // the shares below
         constexpr int U = 8;
         double lmax = 0.0;
         for (int base = 0; base < p.m; base += U * kBlock) {
@@ -616,8 +624,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     }
     const double tau0 = (p.tol_mode == L0_TOL_RELATIVE) ? p.tol * ymax : p.tol;
     if (local_init) {
-        // ||y||_0 and the bucket words of r = y: all of them into LDS, this
-        // workgroup's share also to the global word array
+        // ||y||_0 and the bucket words of r = y, all of them into LDS
         const double iw = 1.0 / bucket_width(tau0, ymax);
         constexpr int U = 8;
         int cnt = 0;
@@ -635,6 +642,20 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             }
         }
         nnz = block_sum(cnt);
+    }
+
+    // the member count and the barrier sites; work is split by member id
+    const int state = admit_complete(c, site, reg, adm.window, limit);
+    const int64_t gtid = static_cast<int64_t>(site.member) * kBlock + tid;
+    const int64_t gsize = static_cast<int64_t>(site.count) * kBlock;
+    if (state < 0) {
+        if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
+        return;
+    }
+    if (p.timeline && site.member == 0 && tid == 0)
+        p.timeline[3 * p.max_iter + 7] = static_cast<int64_t>(wall_clock64());
+    if (local_init) {
+        // this workgroup's share of the words to the global word array
         for (int64_t i = gtid; i < p.m; i += gsize) static_cast<uint32_t*>(p.rword)[i] = lds_w[i];
         if (gtid == 0) __hip_atomic_store(&c->nnz, nnz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
