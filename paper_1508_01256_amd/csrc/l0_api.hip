@@ -522,7 +522,7 @@ bool problems_ok(const l0_problem* probs, int32_t count, BatchPlan& pl, bool buf
     size_t off = 0;
     for (int32_t i = 0; i < count; ++i) {
         pl.inst_off[i] = static_cast<int64_t>(off);
-        off += l0::inst_layout(probs[i].n, probs[i].m, probs[i].n * probs[i].d).total;
+        off += l0::inst_layout(probs[i].n, probs[i].m, probs[i].d).total;
     }
     pl.scratch = off;
     return true;

@@ -12,13 +12,25 @@ namespace l0 {
 // Byte offsets, within one instance's scratch region, of its working arrays
 // (sized by that instance alone).
 struct InstLayout {
-    size_t r, rword, member, slot_cnt, slot_sorted, aff_flag, aff_list, row_off, slots, overflow;
+    size_t r, rword, member, slot_cnt, slot_sorted, aff_flag, aff_list, row_off, slots, overflow, soa;
     size_t total;
 };
 
 __host__ __device__ inline size_t align256_hd(size_t b) { return (b + 255) & ~size_t(255); }
 
-__host__ __device__ inline InstLayout inst_layout(int64_t n, int32_t m, int64_t nd) {
+// The instance's repacked index store, which its votes stream: chunks of 64
+// 32-bit words per neighbour plane.  16-bit rows (m <= 65536): a chunk holds
+// 128 columns, word w of plane t the t-th rows of columns 2w (low half) and
+// 2w + 1 (high half); 32-bit rows: 64 columns, word w the row of column w.
+// Chunk c's plane t starts at 32-bit word (c*d + t)*64.
+__host__ __device__ inline bool batch_rows16(int32_t m) { return m <= 65536; }
+__host__ __device__ inline int64_t batch_chunk_cols(int32_t m) { return batch_rows16(m) ? 128 : 64; }
+__host__ __device__ inline int64_t batch_chunks(int64_t n, int32_t m) {
+    return (n + batch_chunk_cols(m) - 1) / batch_chunk_cols(m);
+}
+
+__host__ __device__ inline InstLayout inst_layout(int64_t n, int32_t m, int32_t d) {
+    const int64_t nd = n * d;
     InstLayout L{};
     size_t o = 0;
     L.r = o;
@@ -41,6 +53,8 @@ __host__ __device__ inline InstLayout inst_layout(int64_t n, int32_t m, int64_t 
     o += align256_hd(static_cast<size_t>(nd) * 4);
     L.overflow = o;
     o += align256_hd(static_cast<size_t>(n) * 4);
+    L.soa = o;
+    o += static_cast<size_t>(batch_chunks(n, m)) * d * 256;
     L.total = o;
     return L;
 }

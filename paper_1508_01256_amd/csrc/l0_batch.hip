@@ -11,9 +11,12 @@
 // instance's control block (a bounded wait).  Every instance has scratch of
 // its own size.
 //
-// The vote streams the caller's column-index store directly: each wave keeps
-// several 64-column groups of indices in flight and transposes each group
-// through LDS.  Row bucket words (l0_filter.h) sit in every member's LDS when
+// The setup pass over the caller's column-index store (degree counts and
+// input checks; each wave transposes 64-column groups through LDS, so that a
+// lane holds one column's rows) also writes the instance's repacked index
+// store: one coalesced plane per neighbour, 16-bit rows when m <= 65536.
+// The votes stream that store, several chunks in flight per wave, with no
+// transpose.  Row bucket words (l0_filter.h) sit in every member's LDS when
 // m fits the launch's word capacity.  Scoring, updates and residual
 // recomputation are the single-instance decoder's (l0_filter.h,
 // l0_common.h), so every instance's result is bitwise the one it gets alone.
@@ -66,10 +69,11 @@ struct BlockState {
     gptr<int32_t> row_off;
     gptr<int32_t> slots;
     gptr<int32_t> overflow;
+    gptr<uint32_t> soa;       // repacked index store (batch_chunks of d planes)
 };
 
 __device__ BlockState carve(char* base, const l0_problem& P) {
-    const InstLayout lay = inst_layout(P.n, P.m, P.n * P.d);
+    const InstLayout lay = inst_layout(P.n, P.m, P.d);
     BlockState s{};
     s.x = global(P.x_out);
     s.y = global(P.y);
@@ -85,6 +89,7 @@ __device__ BlockState carve(char* base, const l0_problem& P) {
     s.row_off = global(reinterpret_cast<int32_t*>(base + lay.row_off));
     s.slots = global(reinterpret_cast<int32_t*>(base + lay.slots));
     s.overflow = global(reinterpret_cast<int32_t*>(base + lay.overflow));
+    s.soa = global(reinterpret_cast<uint32_t*>(base + lay.soa));
     return s;
 }
 
@@ -212,74 +217,86 @@ __device__ __forceinline__ void load_group(gptr<const int32_t> col_idx, int64_t 
     }
 }
 
-// One vote pass over this member's columns: groups first, first + stride,
-// ... for wave 0, each wave of the member starting one group later.
-// SPILL = false: each wave appends the columns passing the bucket filter to
-// its LDS queue segment and counts them in wq[wave], also past the segment's
-// capacity (those are not kept).  SPILL = true: every passing column goes to
-// the team's shared global list, counted in *spill; this pass runs only
-// after a segment overflowed.
+// Neighbour planes of chunk c of the repacked store: one coalesced 32-bit
+// load per plane.  The chunk number is clamped into the store, so the load is
+// unconditional (no branch for the wait counters to merge over); a clamped
+// chunk's columns are >= n and never pass.
+template <int D>
+__device__ __forceinline__ void load_chunk(gptr<const uint32_t> soa, int64_t c, int64_t last, int lane,
+                                           uint32_t (&out)[D]) {
+    const gptr<const uint32_t> q = soa + (c < last ? c : last) * (64 * D) + lane;
+#pragma unroll
+    for (int t = 0; t < D; ++t) out[t] = __builtin_nontemporal_load(q + t * 64);
+}
+
+// One vote pass over this member's columns: chunks first, first + stride,
+// ... for wave 0, each wave of the member starting one chunk later, kDepth
+// chunks in flight per wave.  SPILL = false: each wave appends the columns
+// passing the bucket filter to its LDS queue segment and counts them in
+// wq[wave], also past the segment's capacity (those are not kept).  SPILL =
+// true: every passing column goes to the team's shared global list, counted
+// in *spill; this pass runs only after a segment overflowed.
 //
 // The ordinary pass has no branch and no global write in its loop body:
 // either would make the compiler drain all outstanding loads at the loop
-// head, serialising the index prefetch.  Lanes with nothing to queue store
-// to their discard slot instead.  WM: bucket words in LDS as 32-bit words
-// (1) or folded 16-bit words (2, twice as many rows), else (0) in global
-// memory.  Slots past the last group run on clamped indices and queue
-// nothing.
-template <int D, int WM, bool SPILL>
-__device__ void vote_pass(gptr<const int32_t> col_idx, int64_t n, const BlockState& s, const Lds& L, int a, int rule,
-                          int64_t first, int64_t stride, gptr<int> spill) {
-    // groups in flight per wave: about 32 registers of indices
+// head, serialising the prefetch.  Lanes with nothing to queue store to
+// their discard slot instead.  WM: bucket words in LDS as 32-bit words (1)
+// or folded 16-bit words (2, twice as many rows), else (0) in global memory.
+// R16: 16-bit rows, two columns per lane and chunk.  Columns >= n (the last
+// chunk's padding, clamped chunks) gather row 0 and queue nothing.
+template <int D, int WM, bool R16, bool SPILL>
+__device__ void vote_pass(int64_t n, const BlockState& s, const Lds& L, int a, int rule, int64_t first,
+                          int64_t stride, gptr<int> spill) {
+    // chunks in flight per wave: about 32 registers of indices
     constexpr int kDepth = D <= 8 ? 4 : (D <= 10 ? 3 : (D <= 16 ? 2 : 1));
+    constexpr int kCols = R16 ? 128 : 64;
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     // the wave index is uniform across the wave: a scalar loop (no exec mask)
     const int wid = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int qcap = kBatchQueue / nw;
     const lptr<int> seg = L.queue + wid * (qcap + 64);
-    const int64_t nd = n * D;
-    const int64_t ngroups = (n + 63) >> 6;
-    const lptr<int> stage = L.stage + wid * (64 * D);
+    const int64_t nchunks = (n + kCols - 1) / kCols, last = nchunks - 1;
+    const gptr<const uint32_t> soa = s.soa;
     const unsigned long long below = (1ull << lane) - 1ull;
-    const int64_t g_first = first + wid, g_step = kDepth * stride;
+    const int64_t c_first = first + wid, c_step = kDepth * stride;
     int count = 0;  // wave-uniform
-    int buf[kDepth][D];
+    uint32_t buf[kDepth][D];
 #pragma unroll
-    for (int sl = 0; sl < kDepth; ++sl) load_group<D>(col_idx, g_first + sl * stride, nd, lane, buf[sl]);
-    for (int64_t g0 = g_first; g0 < ngroups; g0 += g_step) {
+    for (int sl = 0; sl < kDepth; ++sl) load_chunk<D>(soa, c_first + sl * stride, last, lane, buf[sl]);
+    for (int64_t c0 = c_first; c0 < nchunks; c0 += c_step) {
 #pragma unroll
         for (int sl = 0; sl < kDepth; ++sl) {
-            const int64_t g = g0 + sl * stride;
+            const int64_t c = c0 + sl * stride;
+            uint32_t rw[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) stage[k * 64 + lane] = buf[sl][k];
-            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-            __builtin_amdgcn_wave_barrier();
-            uint32_t w[D];
+            for (int t = 0; t < D; ++t) rw[t] = buf[sl][t];
+            // refill this slot (the copy above waited for its loads)
+            load_chunk<D>(soa, c + c_step, last, lane, buf[sl]);
 #pragma unroll
-            for (int t = 0; t < D; ++t) {
-                const int row = stage[lane * D + t];
-                w[t] = WM == 1 ? L.words[row] : (WM == 2 ? unfold_word(L.hwords[row]) : s.rword[row]);
-            }
-            // refill this slot after the gathers are issued (the scheduler may
-            // not hoist it): the gathers never wait for it, and it is in
-            // flight while the filter runs
-            __builtin_amdgcn_sched_barrier(0);
-            load_group<D>(col_idx, g + g_step, nd, lane, buf[sl]);
-            __builtin_amdgcn_wave_barrier();
-            const int64_t j = g * 64 + lane;
-            const bool pass = bucket_filter<D>(w, a, rule) && j < n;
-            const unsigned long long mask = __ballot(pass);
-            if (SPILL) {
-                if (mask) {
-                    int qb = 0;
-                    if (lane == 0) qb = fetch_add(spill, __popcll(mask));
-                    qb = __shfl(qb, 0);
-                    if (pass) s.overflow[qb + __popcll(mask & below)] = static_cast<int>(j);
+            for (int h = 0; h < (R16 ? 2 : 1); ++h) {
+                const int64_t j = R16 ? c * kCols + 2 * lane + h : c * kCols + lane;
+                const bool in = j < n;
+                uint32_t w[D];
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    const uint32_t r = R16 ? (h ? rw[t] >> 16 : rw[t] & 0xFFFFu) : rw[t];
+                    const uint32_t row = in ? r : 0u;
+                    w[t] = WM == 1 ? L.words[row] : (WM == 2 ? unfold_word(L.hwords[row]) : s.rword[row]);
                 }
-            } else {
-                const int pos = count + __popcll(mask & below);
-                seg[(pass && pos < qcap) ? pos : qcap + lane] = static_cast<int>(j);
-                count += __popcll(mask);
+                const bool pass = bucket_filter<D>(w, a, rule) && in;
+                const unsigned long long mask = __ballot(pass);
+                if (SPILL) {
+                    if (mask) {
+                        int qb = 0;
+                        if (lane == 0) qb = fetch_add(spill, __popcll(mask));
+                        qb = __shfl(qb, 0);
+                        if (pass) s.overflow[qb + __popcll(mask & below)] = static_cast<int>(j);
+                    }
+                } else {
+                    const int pos = count + __popcll(mask & below);
+                    seg[(pass && pos < qcap) ? pos : qcap + lane] = static_cast<int>(j);
+                    count += __popcll(mask);
+                }
             }
         }
     }
@@ -305,12 +322,12 @@ __device__ void score_column(gptr<const int32_t> col_idx, const BlockState& s, i
 // The vote of one iteration for this member, with the exact scoring of the
 // columns it queued in LDS.  Returns true when its queue overflowed: its
 // columns then went to the team's shared list, scored after a team barrier.
-template <int D, int WM>
+template <int D, int WM, bool R16>
 __device__ bool vote_and_score(gptr<const int32_t> col_idx, int64_t n, const BlockState& s, const Lds& L, int a,
                                int rule, const Team& tm, gptr<IterCounters> ring, double tau, int pos) {
     const int nw = blockDim.x >> 6, qcap = kBatchQueue / nw;
     const int64_t first = static_cast<int64_t>(tm.rank) * nw, stride = static_cast<int64_t>(tm.size) * nw;
-    vote_pass<D, WM, false>(col_idx, n, s, L, a, rule, first, stride, nullptr);
+    vote_pass<D, WM, R16, false>(n, s, L, a, rule, first, stride, nullptr);
     __syncthreads();
     int total = 0;
     bool over = false;
@@ -319,7 +336,7 @@ __device__ bool vote_and_score(gptr<const int32_t> col_idx, int64_t n, const Blo
         over |= L.wq[w] > qcap;
     }
     if (over) {
-        vote_pass<D, WM, true>(col_idx, n, s, L, a, rule, first, stride, &ring->spill);
+        vote_pass<D, WM, R16, true>(n, s, L, a, rule, first, stride, &ring->spill);
         return true;
     }
     for (int q = threadIdx.x; q < total; q += blockDim.x) {
@@ -574,6 +591,7 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
     // bucket words in LDS: 32-bit when m fits the word capacity, folded to
     // 16 bits when it fits twice over, else read from global memory
     const int wm = m <= bp.words_cap ? 1 : (m <= 2 * bp.words_cap ? 2 : 0);
+    const bool r16 = batch_rows16(m);
     const int64_t gt = static_cast<int64_t>(rank) * nthr + tid, gstep = static_cast<int64_t>(tsize) * nthr;
 
     // --- init, split over the team: x_hat = 0, support bitmap, per-row
@@ -640,11 +658,25 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
             __builtin_amdgcn_s_waitcnt(0xC07F);
             __builtin_amdgcn_wave_barrier();
             const bool col = g * 64 + lane < n;  // slots past the last column hold no column
-            if (lo == 0 && col) {
+            if (lo == 0) {
+                if (col) {
 #pragma unroll
-                for (int t = 0; t < D; ++t)
-                    if (r[t] < 0 || r[t] >= m) bad_idx |= kErrBadIndex;
-                if (has_repeat<D>(r)) bad_idx |= kErrRepeatedRow;
+                    for (int t = 0; t < D; ++t)
+                        if (r[t] < 0 || r[t] >= m) bad_idx |= kErrBadIndex;
+                    if (has_repeat<D>(r)) bad_idx |= kErrRepeatedRow;
+                }
+                // the repacked store (rows of lanes past the last column
+                // are padding; a bad index is stored truncated, and the
+                // instance ends with an input error before any vote)
+                if (r16) {
+                    const gptr<uint16_t> p16 = (gptr<uint16_t>)s.soa + (g >> 1) * (128 * D) + (g & 1) * 64 + lane;
+#pragma unroll
+                    for (int t = 0; t < D; ++t) p16[t * 128] = static_cast<uint16_t>(r[t]);
+                } else {
+                    const gptr<uint32_t> p32 = s.soa + g * (64 * D) + lane;
+#pragma unroll
+                    for (int t = 0; t < D; ++t) p32[t * 64] = static_cast<uint32_t>(r[t]);
+                }
             }
 #pragma unroll
             for (int t = 0; t < D; ++t) {
@@ -745,10 +777,11 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         __syncthreads();
 
         // vote and exact scoring of this member's columns (Jacobi updates)
-        const bool spilled = wm == 1   ? vote_and_score<D, 1>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos)
-                             : wm == 2 ? vote_and_score<D, 2>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos)
-                                       : vote_and_score<D, 0>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos);
-        (void)spilled;
+        // (16-bit rows whenever the words are in LDS: m <= 2 * words_cap <= 65536)
+        if (wm == 1) vote_and_score<D, 1, true>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos);
+        else if (wm == 2) vote_and_score<D, 2, true>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos);
+        else if (r16) vote_and_score<D, 0, true>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos);
+        else vote_and_score<D, 0, false>(col_idx, n, s, L, a, bp.rule, tm, ring, tau, pos);
         if (lead && tid == 0) {
             const gptr<IterCounters> next = &tm.ctl->ring[(pass + 1) % 3];
             next->tcount = 0;
