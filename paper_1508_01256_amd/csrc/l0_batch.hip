@@ -138,13 +138,20 @@ __device__ double wg_max(double v, lptr<double> red) {
 }
 
 // Exclusive prefix sum of a[0..len) (LDS) plus carry into out[0..len);
-// returns the new carry.  All threads call it.
+// returns the new carry.  All threads call it; each takes four consecutive
+// entries per round.
 __device__ int wg_scan_to(lptr<const int> a, int len, gptr<int32_t> out, int carry, lptr<int> red) {
+    constexpr int E = 4;
     const int nw = blockDim.x >> 6, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int base = 0; base < len; base += blockDim.x) {
-        const int i = base + threadIdx.x;
-        const int v = i < len ? a[i] : 0;
-        int incl = v;
+    for (int base = 0; base < len; base += blockDim.x * E) {
+        const int i0 = base + threadIdx.x * E;
+        int v[E], tsum = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            v[e] = i0 + e < len ? a[i0 + e] : 0;
+            tsum += v[e];
+        }
+        int incl = tsum;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const int o = __shfl_up(incl, off);
@@ -153,12 +160,14 @@ __device__ int wg_scan_to(lptr<const int> a, int len, gptr<int32_t> out, int car
         __syncthreads();
         if (lane == 63) red[wid] = incl;
         __syncthreads();
-        int before = carry;
-        for (int w = 0; w < wid; ++w) before += red[w];
-        if (i < len) out[i] = before + incl - v;
-        int total = carry;
-        for (int w = 0; w < nw; ++w) total += red[w];
-        carry = total;
+        int run = carry + incl - tsum;
+        for (int w = 0; w < wid; ++w) run += red[w];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (i0 + e < len) out[i0 + e] = run;
+            run += v[e];
+        }
+        for (int w = 0; w < nw; ++w) carry += red[w];
     }
     return carry;
 }
@@ -260,9 +269,17 @@ __device__ void vote_pass(int64_t n, const BlockState& s, const Lds& L, int a, i
     const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t c_first = first + wid, c_step = kDepth * stride;
     int count = 0;  // wave-uniform
+    // The slots' loads are issued in slot order and each slot is refilled
+    // right after it is consumed, so the oldest loads in flight are always
+    // the next slot's: every wait is for one slot only.  Scheduling barriers
+    // keep the compiler from reordering the batches (a slot issued out of
+    // order would make its wait cover the slots after it as well).
     uint32_t buf[kDepth][D];
 #pragma unroll
-    for (int sl = 0; sl < kDepth; ++sl) load_chunk<D>(soa, c_first + sl * stride, last, lane, buf[sl]);
+    for (int sl = 0; sl < kDepth; ++sl) {
+        load_chunk<D>(soa, c_first + sl * stride, last, lane, buf[sl]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
     for (int64_t c0 = c_first; c0 < nchunks; c0 += c_step) {
 #pragma unroll
         for (int sl = 0; sl < kDepth; ++sl) {
@@ -271,7 +288,9 @@ __device__ void vote_pass(int64_t n, const BlockState& s, const Lds& L, int a, i
 #pragma unroll
             for (int t = 0; t < D; ++t) rw[t] = buf[sl][t];
             // refill this slot (the copy above waited for its loads)
+            __builtin_amdgcn_sched_barrier(0);
             load_chunk<D>(soa, c + c_step, last, lane, buf[sl]);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int h = 0; h < (R16 ? 2 : 1); ++h) {
                 const int64_t j = R16 ? c * kCols + 2 * lane + h : c * kCols + lane;
@@ -562,6 +581,148 @@ __device__ __forceinline__ int64_t stamp() {
     return static_cast<int64_t>(wall_clock64());
 }
 
+// Groups of 64 columns in flight per wave in the setup passes.
+template <int D>
+struct SetupDepth {
+    static constexpr int kH = D <= 8 ? 4 : (D <= 12 ? 3 : 2);
+};
+
+// Rows r[0..D) of lane `lane`'s column in group g into the repacked store,
+// with raw buffer stores over the group's own part: a group past the last
+// (ngroups) has an empty range, so every call issues D stores whatever g is
+// and the waits for the index loads count them exactly.
+// A value the whole wave holds, in scalar registers (a buffer resource built
+// from it then needs no per-lane loop).
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+template <int D>
+__device__ __forceinline__ void store_group_rows(gptr<uint32_t> soa, int64_t g, int64_t ngroups, bool r16, int lane,
+                                                 const int (&r)[D]) {
+    constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit dwords (gfx9)
+    const int bytes = __builtin_amdgcn_readfirstlane(g < ngroups ? D * 256 : 0);
+    if (r16) {
+        char* base = (char*)wave_uniform(reinterpret_cast<uint64_t>((char*)soa + (g >> 1) * (256 * D) + (g & 1) * 128));
+        const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, kRsrcWord3);
+#pragma unroll
+        for (int t = 0; t < D; ++t)
+            __builtin_amdgcn_raw_buffer_store_b16(static_cast<unsigned short>(r[t]), rsrc, (t * 128 + lane) * 2, 0, 0);
+    } else {
+        char* base = (char*)wave_uniform(reinterpret_cast<uint64_t>((char*)soa + g * (256 * D)));
+        const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, kRsrcWord3);
+#pragma unroll
+        for (int t = 0; t < D; ++t) __builtin_amdgcn_raw_buffer_store_b32(r[t], rsrc, (t * 64 + lane) * 4, 0, 0);
+    }
+}
+
+// First setup pass over this wave's 64-column groups (g_first, g_first +
+// g_stride, ...) of the caller's column-index store: each group's D
+// coalesced loads are transposed through the wave's LDS staging area, so that
+// a lane holds one column's rows; every row is range-checked, no column may
+// list a row twice (bits into *bad), the rows go to the repacked store, and
+// rows below len are counted in hist.  kH groups in flight, in slots taking
+// turns; slots past the last group load a clamped address and do nothing.
+template <int D>
+__device__ void setup_first_pass(gptr<const int32_t> col_idx, int64_t n, int m, const BlockState& s,
+                                 lptr<int> stage, lptr<int> hist, int len, int64_t g_first, int64_t g_stride,
+                                 bool r16, int& bad) {
+    constexpr int kH = SetupDepth<D>::kH;
+    const int lane = threadIdx.x & 63;
+    const int64_t nd = n * D, ngroups = (n + 63) >> 6;
+    // (slot order kept as in vote_pass)
+    int buf[kH][D];
+#pragma unroll
+    for (int sl = 0; sl < kH; ++sl) {
+        load_group<D>(col_idx, g_first + sl * g_stride, nd, lane, buf[sl]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int64_t g0 = g_first; g0 < ngroups; g0 += kH * g_stride) {
+#pragma unroll
+        for (int sl = 0; sl < kH; ++sl) {
+            const int64_t g = g0 + sl * g_stride;
+#pragma unroll
+            for (int k = 0; k < D; ++k) stage[k * 64 + lane] = buf[sl][k];
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+            __builtin_amdgcn_wave_barrier();
+            int r[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) r[t] = stage[lane * D + t];
+            // every lane has read its column before the next group's stores
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            load_group<D>(col_idx, g + kH * g_stride, nd, lane, buf[sl]);
+            __builtin_amdgcn_sched_barrier(0);
+            const bool col = g * 64 + lane < n;  // slots past the last column hold no column
+            if (col) {
+#pragma unroll
+                for (int t = 0; t < D; ++t)
+                    if (r[t] < 0 || r[t] >= m) bad |= kErrBadIndex;
+                if (has_repeat<D>(r)) bad |= kErrRepeatedRow;
+            }
+            // (rows of lanes past the last column are padding; a bad index
+            // is stored truncated, and the instance ends with an input error
+            // before any vote)
+            store_group_rows<D>(s.soa, g, ngroups, r16, lane, r);
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+                if (col && r[t] >= 0 && r[t] < len) fetch_add(&hist[r[t]], 1);
+        }
+    }
+    // the stores are done before this wave reads them back (later passes)
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+}
+
+// A later setup pass (rows lo .. lo+len-1 counted in hist): each wave reads
+// back the rows of its own groups from the repacked store (written by this
+// wave in the first pass), D coalesced loads per group, kH groups in flight.
+template <int D>
+__device__ void setup_count_pass(int64_t n, const BlockState& s, lptr<int> hist, int lo, int len, int64_t g_first,
+                                 int64_t g_stride, bool r16) {
+    constexpr int kH = SetupDepth<D>::kH;
+    const int lane = threadIdx.x & 63;
+    const int64_t ngroups = (n + 63) >> 6;
+    auto load = [&](int64_t g, uint32_t (&out)[D]) {
+        const int64_t gc = g < ngroups ? g : ngroups - 1;
+        if (r16) {
+            const gptr<const uint16_t> q = (gptr<const uint16_t>)s.soa + (gc >> 1) * (128 * D) + (gc & 1) * 64 + lane;
+#pragma unroll
+            for (int t = 0; t < D; ++t) out[t] = q[t * 128];
+        } else {
+            const gptr<const uint32_t> q = s.soa + gc * (64 * D) + lane;
+#pragma unroll
+            for (int t = 0; t < D; ++t) out[t] = q[t * 64];
+        }
+    };
+    uint32_t buf[kH][D];
+#pragma unroll
+    for (int sl = 0; sl < kH; ++sl) {
+        load(g_first + sl * g_stride, buf[sl]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int64_t g0 = g_first; g0 < ngroups; g0 += kH * g_stride) {
+#pragma unroll
+        for (int sl = 0; sl < kH; ++sl) {
+            const int64_t g = g0 + sl * g_stride;
+            uint32_t r[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) r[t] = buf[sl][t];
+            __builtin_amdgcn_sched_barrier(0);
+            load(g + kH * g_stride, buf[sl]);
+            __builtin_amdgcn_sched_barrier(0);
+            const bool col = g * 64 + lane < n;
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                const int rel = static_cast<int>(r[t]) - lo;
+                if (col && rel >= 0 && rel < len) fetch_add(&hist[rel], 1);
+            }
+        }
+    }
+}
+
 // One member's part of decoding instance P.  Not inlined: each degree gets
 // its own register allocation inside the range kernels (the call costs one
 // register save per work item).
@@ -587,7 +748,6 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
     const gptr<const int32_t> col_idx = global(P.col_idx);
     const int64_t n = P.n;
     const int m = P.m;
-    const int64_t nd = n * D;
     // bucket words in LDS: 32-bit when m fits the word capacity, folded to
     // 16 bits when it fits twice over, else read from global memory
     const int wm = m <= bp.words_cap ? 1 : (m <= 2 * bp.words_cap ? 2 : 0);
@@ -605,14 +765,26 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
     for (int64_t w = gt; w < ((n + 31) >> 5); w += gstep) s.member[w] = 0u;
     double lmax = 0.0;
     int bad = 0;
-    for (int64_t i = gt; i < m; i += gstep) {
-        const double yi = s.y[i];
-        if (!isfinite(yi)) bad = 1;
-        else lmax = fmax(lmax, fabs(yi));
-        s.r[i] = yi;
-        s.slot_cnt[i] = 0;
-        s.slot_sorted[i] = 0;
-        s.aff_flag[i] = 0;
+    {
+        constexpr int U = 4;  // y loads in flight per thread
+        for (int64_t i0 = gt; i0 < m; i0 += U * gstep) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = s.y[min(i0 + u * gstep, static_cast<int64_t>(m) - 1)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = i0 + u * gstep;
+                if (i < m) {
+                    const double yi = v[u];
+                    if (!isfinite(yi)) bad = 1;
+                    else lmax = fmax(lmax, fabs(yi));
+                    s.r[i] = yi;
+                    s.slot_cnt[i] = 0;
+                    s.slot_sorted[i] = 0;
+                    s.aff_flag[i] = 0;
+                }
+            }
+        }
     }
     lmax = wg_max(lmax, (lptr<double>)L.red);
     bad = wg_sum(bad, L.red);
@@ -627,17 +799,16 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
 
     // --- row degrees -> row_off (exclusive scan), counted in LDS one range
     //     of words_cap rows at a time over this member's share of the
-    //     columns; a team adds its counts in slot_cnt and the leader scans.
-    //     Each wave reads 64-column groups as the vote does (D coalesced
-    //     loads, transposed through its LDS staging area, two groups in
-    //     flight), so every lane holds one column's rows: the first pass
-    //     range-checks every row and checks that no column lists a row twice.
+    //     columns.  The first pass reads the caller's store (and checks it
+    //     and writes the repacked store, see setup_first_pass), later ones
+    //     read the repacked store back.  A team adds its counts in slot_cnt;
+    //     each member then scans a slice of the rows, and the slices are
+    //     joined by their totals.
     const int hcap = bp.words_cap;
     const lptr<int> hist = (lptr<int>)L.words;
     const int lane = tid & 63, nw = nthr >> 6;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const lptr<int> stage = L.stage + wid * (64 * D);
-    const int64_t ngroups = (n + 63) >> 6;
     const int64_t g_first = static_cast<int64_t>(rank) * nw + wid, g_stride = static_cast<int64_t>(tsize) * nw;
     int bad_idx = 0;
     int carry = 0;
@@ -645,55 +816,10 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         const int len = min(hcap, m - lo);
         for (int i = tid; i < len; i += nthr) hist[i] = 0;
         __syncthreads();
-        // one group: stage, read back this lane's column, count its rows
-        auto count_group = [&](const int (&buf)[D], int64_t g) {
-#pragma unroll
-            for (int k = 0; k < D; ++k) stage[k * 64 + lane] = buf[k];
-            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-            __builtin_amdgcn_wave_barrier();
-            int r[D];
-#pragma unroll
-            for (int t = 0; t < D; ++t) r[t] = stage[lane * D + t];
-            // every lane has read its column before the next group's stores
-            __builtin_amdgcn_s_waitcnt(0xC07F);
-            __builtin_amdgcn_wave_barrier();
-            const bool col = g * 64 + lane < n;  // slots past the last column hold no column
-            if (lo == 0) {
-                if (col) {
-#pragma unroll
-                    for (int t = 0; t < D; ++t)
-                        if (r[t] < 0 || r[t] >= m) bad_idx |= kErrBadIndex;
-                    if (has_repeat<D>(r)) bad_idx |= kErrRepeatedRow;
-                }
-                // the repacked store (rows of lanes past the last column
-                // are padding; a bad index is stored truncated, and the
-                // instance ends with an input error before any vote)
-                if (r16) {
-                    const gptr<uint16_t> p16 = (gptr<uint16_t>)s.soa + (g >> 1) * (128 * D) + (g & 1) * 64 + lane;
-#pragma unroll
-                    for (int t = 0; t < D; ++t) p16[t * 128] = static_cast<uint16_t>(r[t]);
-                } else {
-                    const gptr<uint32_t> p32 = s.soa + g * (64 * D) + lane;
-#pragma unroll
-                    for (int t = 0; t < D; ++t) p32[t * 64] = static_cast<uint32_t>(r[t]);
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < D; ++t) {
-                const int rel = r[t] - lo;
-                if (col && rel >= 0 && rel < len) fetch_add(&hist[rel], 1);
-            }
-        };
-        int ga[D], gb[D];
-        load_group<D>(col_idx, g_first, nd, lane, ga);
-        load_group<D>(col_idx, g_first + g_stride, nd, lane, gb);
-        for (int64_t g = g_first; g < ngroups; g += 2 * g_stride) {
-            count_group(ga, g);
-            load_group<D>(col_idx, g + 2 * g_stride, nd, lane, ga);
-            if (g + g_stride >= ngroups) break;
-            count_group(gb, g + g_stride);
-            load_group<D>(col_idx, g + 3 * g_stride, nd, lane, gb);
-        }
+        if (lo == 0)
+            setup_first_pass<D>(col_idx, n, m, s, stage, hist, len, g_first, g_stride, r16, bad_idx);
+        else
+            setup_count_pass<D>(n, s, hist, lo, len, g_first, g_stride, r16);
         __syncthreads();
         if (tsize == 1) {
             carry = wg_scan_to(hist, len, s.row_off + lo, carry, L.red);
@@ -711,22 +837,37 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         if (lane == 0 && wbad) __hip_atomic_fetch_or(&tm.ctl->bad, wbad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (tsize > 1) {
+        // member `rank` scans rows [r0, r1) from zero and posts the slice
+        // total (in the instance's overflow list, unused until the votes);
+        // after a team barrier it adds the totals of the slices before it
         alive = alive && team_sync(tm, L);
-        if (alive && lead) {
+        const int r0 = static_cast<int>(static_cast<int64_t>(m) * rank / tsize);
+        const int r1 = static_cast<int>(static_cast<int64_t>(m) * (rank + 1) / tsize);
+        if (alive) {
             const lptr<int> chunk = (lptr<int>)L.words;
-            for (int lo = 0; lo < m; lo += hcap) {
-                const int len = min(hcap, m - lo);
+            int c2 = 0;
+            for (int lo = r0; lo < r1; lo += hcap) {
+                const int len = min(hcap, r1 - lo);
                 for (int i = tid; i < len; i += nthr) {
                     chunk[i] = load_agent(&s.slot_cnt[lo + i]);
                     s.slot_cnt[lo + i] = 0;
                 }
                 __syncthreads();
-                carry = wg_scan_to(chunk, len, s.row_off + lo, carry, L.red);
+                c2 = wg_scan_to(chunk, len, s.row_off + lo, c2, L.red);
                 __syncthreads();
             }
+            if (tid == 0) s.overflow[rank] = c2;
+        }
+        alive = alive && team_sync(tm, L);
+        if (alive) {
+            // (tsize <= kMaxTeam <= blockDim.x: one slice total per thread)
+            const int base = wg_sum(tid < rank ? load_agent(&s.overflow[tid]) : 0, L.red);
+            if (base)
+                for (int i = r0 + tid; i < r1; i += nthr) s.row_off[i] += base;
+            if (rank == tsize - 1 && tid == 0) carry = base + load_agent(&s.overflow[rank]);
         }
     }
-    if (lead && tid == 0) s.row_off[m] = carry;
+    if (rank == tsize - 1 && tid == 0) s.row_off[m] = carry;
     alive = alive && team_sync(tm, L);
     const int flags = load_agent(&tm.ctl->bad);
     if (!alive || flags) {
@@ -741,15 +882,37 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
     const int a = static_cast<int>(ceil(P.alpha));
     // bucket words: every member keeps all of them in LDS (when m fits);
     // the global copy and ||y||_0 are split over the team
-    if (wm == 1)
-        for (int i = tid; i < m; i += nthr) L.words[i] = row_word(s.y[i], tau, inv_w);
-    else if (wm == 2)
-        for (int i = tid; i < m; i += nthr) L.hwords[i] = fold_word(row_word(s.y[i], tau, inv_w));
+    // (y in rounds of U loads in flight per thread)
+    constexpr int U = 8;
+    if (wm) {
+        for (int i0 = tid; i0 < m; i0 += U * nthr) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = s.y[min(i0 + u * nthr, m - 1)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * nthr;
+                if (i < m) {
+                    const uint32_t w = row_word(v[u], tau, inv_w);
+                    if (wm == 1) L.words[i] = w;
+                    else L.hwords[i] = fold_word(w);
+                }
+            }
+        }
+    }
     int nzc = 0;
-    for (int64_t i = gt; i < m; i += gstep) {
-        const double yi = s.y[i];
-        s.rword[i] = row_word(yi, tau, inv_w);
-        nzc += fabs(yi) > tau;
+    for (int64_t i0 = gt; i0 < m; i0 += U * gstep) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = s.y[min(i0 + u * gstep, static_cast<int64_t>(m) - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * gstep;
+            if (i < m) {
+                s.rword[i] = row_word(v[u], tau, inv_w);
+                nzc += fabs(v[u]) > tau;
+            }
+        }
     }
     nzc = wg_sum(nzc, L.red);
     if (tid == 0) fetch_add(&tm.ctl->nnz, nzc);
