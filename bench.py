@@ -177,7 +177,7 @@ def main():
     ap.add_argument("--phase-out", default="", help="phase: also write a markdown summary here")
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: server workspace budget")
-    ap.add_argument("--serve-inflight", type=int, default=4, help="serve: server batches in flight (1..4)")
+    ap.add_argument("--serve-inflight", type=int, default=2, help="serve: server batches in flight (1..4)")
     ap.add_argument("--serve-loads", default="0.5,0.9,1.5", help="serve: loads as fractions of plain capacity")
     ap.add_argument("--sweep-count", type=int, default=4096)
     ap.add_argument("--autotune", action="store_true", help="sweep: pick the schedule with "

@@ -2,7 +2,8 @@
 // decoding requests on top of l0_decode_batched, under a fixed budget of
 // device memory.
 //
-// Host side only.  Requests wait in a first-come-first-served queue.  Every
+// Host side only.  Requests wait in a first-come-first-served queue (a batch
+// gathers the waiting small requests past any large ones).  Every
 // poll first collects finished requests: a batch writes its results into
 // host memory the device can write, each outcome last (behind a system-scope
 // fence), so a request completes when its own outcome appears there, not
@@ -18,11 +19,14 @@
 // device's resident workgroups (one share per slot), so that all of them fit
 // on the device at once and no team waits for members that cannot be
 // scheduled.  A batch of at most kExclusiveMax requests launched while the
-// server is idle gets the whole device instead (lowest latency at low load);
-// nothing else is launched until it has finished.  A large request (at least
-// kSoloIndices column indices) is decoded alone by the single-instance
-// decoder (l0_decode_ex), which streams at the device's full rate; it waits,
-// in arrival order, until no batch is running, and runs alone.
+// server is idle gets the whole device instead (lowest latency at low load).
+// A large request (at least kSoloIndices column indices) is decoded alone by
+// the single-instance decoder (l0_decode_ex), which streams at the device's
+// full rate.  Work that must run alone (a large request, a whole-device
+// batch) is ordered on the device, not by the host: its stream waits for
+// the events of everything launched before it, and work launched while it
+// is in flight waits for its event.  So the device never idles for a host
+// round trip between them, and nothing ever runs beside them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -178,14 +182,31 @@ void collect(l0_server_s* s, bool wait) {
     }
 }
 
+// Make this slot's stream wait for the events of the busy slots: all of them
+// (`all`), or those whose work must run alone.
+hipError_t wait_for_busy(l0_server_s* s, Slot& sl, bool all) {
+    for (Slot& o : s->slots) {
+        if (&o == &sl || !o.busy || !(all || o.exclusive)) continue;
+        const hipError_t e = hipStreamWaitEvent(sl.stream, o.done_event, 0);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Decode the first waiting request alone with the single-instance decoder on
-// this (free) slot; the server is otherwise idle.
-void launch_solo(l0_server_s* s, Slot& sl) {
+// this (free) slot, after everything launched before it.  Returns false,
+// launching nothing, while its workspace does not fit beside the work in
+// flight.
+bool launch_solo(l0_server_s* s, Slot& sl) {
+    const l0_problem& P0 = s->waiting.front().p;
+    const size_t ws = l0_workspace_bytes(P0.n, P0.m, P0.d, P0.max_iter);
+    const size_t at = ws ? find_range(s, ws) : SIZE_MAX;
+    if (at == SIZE_MAX && ws != 0)
+        for (const Slot& o : s->slots)
+            if (o.busy) return false;
     const Request r = s->waiting.front();
     s->waiting.pop_front();
     const l0_problem& P = r.p;
-    const size_t ws = l0_workspace_bytes(P.n, P.m, P.d, P.max_iter);
-    const size_t at = ws ? find_range(s, ws) : SIZE_MAX;
     sl.reqs.assign(1, r);
     sl.done.assign(1, 0);
     sl.remaining = 1;
@@ -201,9 +222,11 @@ void launch_solo(l0_server_s* s, Slot& sl) {
     o.rule = s->opts.batch.rule;
     o.tol_mode = s->opts.batch.tol_mode;
     o.weights = P.weights;
-    l0_status st = at == SIZE_MAX ? L0_ERR_WORKSPACE
-                                  : l0_decode_ex(P.col_idx, P.n, P.m, P.d, P.y, P.alpha, P.max_iter, P.tol,
-                                                 P.x_out, &o, sl.host_res, s->arena + at, ws, sl.stream);
+    l0_status st = at == SIZE_MAX ? L0_ERR_WORKSPACE : L0_OK;
+    if (st == L0_OK && wait_for_busy(s, sl, true) != hipSuccess) st = L0_ERR_HIP;
+    if (st == L0_OK)
+        st = l0_decode_ex(P.col_idx, P.n, P.m, P.d, P.y, P.alpha, P.max_iter, P.tol, P.x_out, &o, sl.host_res,
+                          s->arena + at, ws, sl.stream);
     if (st == L0_OK && hipEventRecord(sl.done_event, sl.stream) != hipSuccess) st = L0_ERR_HIP;
     if (st != L0_OK) {
         (void)hipGetLastError();
@@ -211,6 +234,7 @@ void launch_solo(l0_server_s* s, Slot& sl) {
         fail_rest(s, sl, st);
         release_slot(sl);
     }
+    return true;
 }
 
 // Launch batches into free slots while requests wait.
@@ -221,34 +245,33 @@ l0_status launch(l0_server_s* s) {
         if (s->waiting.empty()) break;
         if (sl.busy) continue;
         int busy = 0;
-        bool exclusive_running = false;
-        for (const Slot& o : s->slots) {
-            busy += o.busy;
-            exclusive_running |= o.busy && o.exclusive;
-        }
-        if (exclusive_running) break;  // wait for the whole-device batch
+        for (const Slot& o : s->slots) busy += o.busy;
         if (is_large(s->waiting.front().p)) {
-            if (busy) break;  // it runs alone
-            launch_solo(s, sl);
-            break;
+            if (!launch_solo(s, sl)) break;  // after everything in flight
+            continue;
         }
-        // take waiting small requests in order while their bound fits a free range
-        size_t bound = 0, take = 0;
-        while (take < s->waiting.size() && take < static_cast<size_t>(max_batch) &&
-               !is_large(s->waiting[take].p)) {
-            const size_t next = bound + s->waiting[take].bound;
+        // take the waiting small requests in arrival order (past waiting
+        // large ones, which are queued one at a time as slots free) while
+        // their bound fits a free range
+        size_t bound = 0;
+        std::vector<size_t> pick;
+        for (size_t q = 0; q < s->waiting.size() && pick.size() < static_cast<size_t>(max_batch); ++q) {
+            if (is_large(s->waiting[q].p)) continue;
+            const size_t next = bound + s->waiting[q].bound;
             if (find_range(s, next) == SIZE_MAX) break;
             bound = next;
-            ++take;
+            pick.push_back(q);
         }
+        const size_t take = pick.size();
         if (take == 0) break;  // wait for a running batch to free its range
         std::vector<l0_problem> probs(take);
-        for (size_t q = 0; q < take; ++q) probs[q] = s->waiting[q].p;
+        for (size_t q = 0; q < take; ++q) probs[q] = s->waiting[pick[q]].p;
         const size_t ws = l0_batch_workspace_bytes(probs.data(), static_cast<int32_t>(take), &s->opts.batch);
         const size_t at = ws ? find_range(s, ws) : SIZE_MAX;
         if (at == SIZE_MAX) return L0_ERR_WORKSPACE;  // the bounds are conservative; not expected
-        sl.reqs.assign(s->waiting.begin(), s->waiting.begin() + static_cast<std::ptrdiff_t>(take));
-        s->waiting.erase(s->waiting.begin(), s->waiting.begin() + static_cast<std::ptrdiff_t>(take));
+        sl.reqs.clear();
+        for (size_t q : pick) sl.reqs.push_back(s->waiting[q]);
+        for (size_t q = take; q-- > 0;) s->waiting.erase(s->waiting.begin() + static_cast<std::ptrdiff_t>(pick[q]));
         sl.done.assign(take, 0);
         sl.remaining = take;
         sl.off = at;
@@ -260,11 +283,13 @@ l0_status launch(l0_server_s* s) {
             sl.host_res[q].outcome = kPending;
         }
         std::atomic_thread_fence(std::memory_order_seq_cst);
-        // the whole device when idle and the batch is small, else one share
+        // the whole device when idle and the batch is small, else one share;
+        // after any work in flight that must run alone
         sl.exclusive = busy == 0 && take <= kExclusiveMax;
-        l0_status st = l0::decode_batched_share(probs.data(), static_cast<int32_t>(take), &s->opts.batch,
-                                                sl.host_res, s->arena + at, ws, sl.stream,
-                                                sl.exclusive ? 1 : nslots);
+        l0_status st = wait_for_busy(s, sl, false) == hipSuccess ? L0_OK : L0_ERR_HIP;
+        if (st == L0_OK)
+            st = l0::decode_batched_share(probs.data(), static_cast<int32_t>(take), &s->opts.batch, sl.host_res,
+                                          s->arena + at, ws, sl.stream, sl.exclusive ? 1 : nslots);
         if (st == L0_OK && hipEventRecord(sl.done_event, sl.stream) != hipSuccess) st = L0_ERR_HIP;
         if (st != L0_OK) {
             (void)hipGetLastError();
@@ -273,8 +298,6 @@ l0_status launch(l0_server_s* s) {
             (void)hipStreamSynchronize(sl.stream);
             fail_rest(s, sl, st);
             release_slot(sl);
-        } else if (sl.exclusive) {
-            break;  // nothing runs beside it
         }
     }
     return L0_OK;

@@ -164,3 +164,20 @@ def test_large_and_small_requests_mixed():
     bufs = upload(insts)
     done = run_server(insts, bufs, budget=4 << 30, max_inflight=2)
     check_against_oracle(insts, bufs, done, "mixed-large")
+
+
+def test_large_requests_queued_on_the_device():
+    """Several large requests in a row, then small ones, through four slots:
+    each large request is queued behind the work in flight (stream order, no
+    host wait) and runs alone; small batches queued behind a large request
+    wait for it.  Every result equals the oracle's."""
+    insts = []
+    for q in range(12):
+        if q < 4 or q % 4 == 0:
+            insts.append(gen.make_instance(29000 + q, 1 << 19, 5243 if q % 2 else 52429, 7, 400))
+        else:
+            insts.append(gen.make_instance(29000 + q, 4000 + 700 * q, 400 + 70 * q, 7, 25))
+    bufs = upload(insts)
+    say("queued large requests", len(insts))
+    done = run_server(insts, bufs, budget=6 << 30, max_inflight=4)
+    check_against_oracle(insts, bufs, done, "queued-large")
