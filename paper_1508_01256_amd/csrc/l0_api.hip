@@ -27,7 +27,8 @@ MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d) {
     b.flag = 256;
     b.partial = repack_lds_hist(m, d) ? 0
                                       : align256(static_cast<size_t>(deg_slices(n, d)) * m * sizeof(int32_t));
-    b.total = b.soa + b.row_off + b.deg + b.flag + b.partial;
+    b.blk = b.partial ? align256(static_cast<size_t>(deg_blocks(m)) * sizeof(int32_t)) : 0;
+    b.total = b.soa + b.row_off + b.deg + b.flag + b.partial + b.blk;
     return b;
 }
 
@@ -118,7 +119,8 @@ l0::MatrixView carve_matrix(char* base, int64_t n, int32_t m, int32_t d) {
     v.row_off = reinterpret_cast<int32_t*>(p);   p += b.row_off;
     v.deg = reinterpret_cast<int32_t*>(p);       p += b.deg;
     v.bad_input = reinterpret_cast<int32_t*>(p); p += b.flag;
-    v.partial = b.partial ? reinterpret_cast<int32_t*>(p) : nullptr;
+    v.partial = b.partial ? reinterpret_cast<int32_t*>(p) : nullptr;  p += b.partial;
+    v.blk = b.blk ? reinterpret_cast<int32_t*>(p) : nullptr;
     v.slices = b.partial ? l0::deg_slices(n, d) : 0;
     return v;
 }

@@ -43,14 +43,17 @@ inline bool rows16(int32_t m) { return m <= 65536; }
 // Degree counting of the matrix preparation.  The repack kernel (waves of
 // kRepackWaves per workgroup, each staging 64 columns) counts row degrees in
 // an LDS histogram when m counts fit beside its staging area.  Otherwise
-// kDegSlices(...) workgroups each count one slice of the index array in LDS,
-// kDegRange rows at a time, and write dense partial counts that a reduction
-// sums: no global atomics (one per index was 0.3 ms at n = 2^20, m = 104858).
+// the index array is cut into deg_slices(...) slices and the rows into ranges
+// of kDegRange; one workgroup per slice and range counts in LDS and writes
+// dense partial counts, which a reduction sums per row (with totals per 1024
+// rows, from which the prefix sum is formed by all workgroups at once): no
+// global atomics (one per index was 0.3 ms at n = 2^20, m = 104858).
 constexpr int kRepackWaves = 16;
 constexpr int kDegRange = 36864;  // rows per LDS pass of the partial counts (144 KiB)
 inline bool repack_lds_hist(int32_t m, int32_t d) {
     return static_cast<size_t>(m) * 4 + static_cast<size_t>(kRepackWaves) * 64 * d * 4 <= kLdsWordBytes;
 }
+inline int64_t deg_blocks(int32_t m) { return (static_cast<int64_t>(m) + 1023) / 1024; }
 inline int deg_slices(int64_t n, int32_t d) {
     const int64_t s = n * d / 8192;  // at least 8192 indices per slice
     return static_cast<int>(s < 1 ? 1 : (s > 64 ? 64 : s));
@@ -74,11 +77,12 @@ struct MatrixView {
     int32_t* deg;       // int32[m] scratch for the degree histogram
     int32_t* bad_input; // int32[1]: kErrBadIndex / kErrRepeatedRow bits found while repacking
     int32_t* partial;   // int32[slices*m] partial degree counts, or nullptr (LDS histogram)
-    int32_t slices;     // workgroups counting partial degrees (0: LDS histogram)
+    int32_t* blk;       // int32[deg_blocks(m)] degree totals per 1024 rows (with partial)
+    int32_t slices;     // slices of the index array counted apart (0: LDS histogram)
 };
 
 struct MatrixBuffers {
-    size_t soa, row_off, deg, flag, partial, total;
+    size_t soa, row_off, deg, flag, partial, blk, total;
 };
 MatrixBuffers matrix_layout(int64_t n, int32_t m, int32_t d);
 

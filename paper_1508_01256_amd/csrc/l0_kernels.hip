@@ -957,42 +957,104 @@ __global__ void __launch_bounds__(1024) repack_kernel(const int32_t* col_idx, Ma
 // partial[s*m + row].  Indices outside [0, m) are skipped (the repack flags
 // them).
 __global__ void __launch_bounds__(1024) deg_partial_kernel(const int32_t* col_idx, MatrixView A, int64_t nd) {
+    // workgroup (x, y): slice x of the index array, rows y*kDegRange ..
     extern __shared__ int hist[];
     constexpr int U = 16;  // independent loads in flight per thread
     const int tid = threadIdx.x;
     const int64_t lo_e = nd * blockIdx.x / gridDim.x, hi_e = nd * (blockIdx.x + 1) / gridDim.x;
-    int32_t* part = A.partial + static_cast<int64_t>(blockIdx.x) * A.m;
-    for (int r0 = 0; r0 < A.m; r0 += kDegRange) {
-        const int len = min(kDegRange, A.m - r0);
-        for (int i = tid; i < len; i += 1024) hist[i] = 0;
-        __syncthreads();
-        for (int64_t base = lo_e; base < hi_e; base += int64_t(1024) * U) {
-            int v[U];
+    const int r0 = static_cast<int>(blockIdx.y) * kDegRange;
+    const int len = min(kDegRange, A.m - r0);
+    for (int i = tid; i < len; i += 1024) hist[i] = 0;
+    __syncthreads();
+    for (int64_t base = lo_e; base < hi_e; base += int64_t(1024) * U) {
+        int v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t e = base + static_cast<int64_t>(u) * 1024 + tid;
-                v[u] = col_idx[e < hi_e ? e : hi_e - 1];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t e = base + static_cast<int64_t>(u) * 1024 + tid;
-                const unsigned rel = static_cast<unsigned>(v[u] - r0);
-                if (e < hi_e && rel < static_cast<unsigned>(len)) atomicAdd(&hist[rel], 1);
-            }
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = base + static_cast<int64_t>(u) * 1024 + tid;
+            v[u] = col_idx[e < hi_e ? e : hi_e - 1];
         }
-        __syncthreads();
-        for (int i = tid; i < len; i += 1024) part[r0 + i] = hist[i];
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = base + static_cast<int64_t>(u) * 1024 + tid;
+            const unsigned rel = static_cast<unsigned>(v[u] - r0);
+            if (e < hi_e && rel < static_cast<unsigned>(len)) atomicAdd(&hist[rel], 1);
+        }
     }
+    __syncthreads();
+    int32_t* part = A.partial + static_cast<int64_t>(blockIdx.x) * A.m + r0;
+    for (int i = tid; i < len; i += 1024) part[i] = hist[i];
 }
 
-// deg[i] = sum over the slices of partial[s*m + i].
-__global__ void __launch_bounds__(256) deg_reduce_kernel(MatrixView A) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= A.m) return;
-    int s = 0;
-    for (int k = 0; k < A.slices; ++k) s += A.partial[static_cast<int64_t>(k) * A.m + i];
-    A.deg[i] = s;
+// Sum of an int over a 1024-thread workgroup (valid in every thread).
+__device__ int block1024_sum(int v, int* s_wave) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s_wave[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int t = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += s_wave[w];
+    return t;
+}
+
+// deg[i] = sum over the slices of partial[s*m + i], 1024 rows per workgroup,
+// and the workgroup's total in blk[blockIdx.x].
+__global__ void __launch_bounds__(1024) deg_reduce_kernel(MatrixView A) {
+    __shared__ int s_wave[16];
+    constexpr int U = 8;  // partial counts in flight per thread
+    const int i = blockIdx.x * 1024 + threadIdx.x;
+    const int ic = i < A.m ? i : A.m - 1;
+    int sum = 0;
+    for (int k0 = 0; k0 < A.slices; k0 += U) {
+        int v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u < A.slices ? k0 + u : A.slices - 1;
+            v[u] = A.partial[static_cast<int64_t>(k) * A.m + ic];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) sum += k0 + u < A.slices ? v[u] : 0;
+    }
+    if (i < A.m) A.deg[i] = sum;
+    const int t = block1024_sum(i < A.m ? sum : 0, s_wave);
+    if (threadIdx.x == 0) A.blk[blockIdx.x] = t;
+}
+
+// row_off from the degrees and the workgroup totals of deg_reduce_kernel:
+// workgroup b adds the totals of the workgroups before it to the exclusive
+// scan of its 1024 degrees; the last one also writes row_off[m].  Workgroup
+// 0 first clears a one-shot decode's solve control block.
+__global__ void __launch_bounds__(1024) scan_blocks_kernel(MatrixView A, int32_t* clear, int64_t clear_count) {
+    __shared__ int s_wave[16];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (blockIdx.x == 0)
+        for (int64_t i = tid; i < clear_count; i += 1024) clear[i] = 0;
+    const int nblk = static_cast<int>(gridDim.x);
+    int before = 0;
+    for (int b0 = 0; b0 < static_cast<int>(blockIdx.x); b0 += 1024)
+        before += b0 + tid < static_cast<int>(blockIdx.x) ? A.blk[b0 + tid] : 0;
+    const int offset = block1024_sum(before, s_wave);
+    const int i = blockIdx.x * 1024 + tid;
+    const int v = i < A.m ? A.deg[i] : 0;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+    }
+    __syncthreads();  // s_wave is reused
+    if (lane == 63) s_wave[wid] = incl;
+    __syncthreads();
+    int run = offset + incl - v;
+    int total = offset;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+        run += w < wid ? s_wave[w] : 0;
+        total += s_wave[w];
+    }
+    if (i < A.m) A.row_off[i] = run;
+    if (blockIdx.x == nblk - 1 && tid == 0) A.row_off[A.m] = total;
 }
 
 // row_off = exclusive prefix sum of the row degrees (one workgroup), chunk by
@@ -1108,16 +1170,19 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s,
     const int cus = device_cus();
     // the degree counts and the bad-index flag follow each other in the
     // matrix buffers: one fill clears both
-    if (A.bad_input > A.deg) {
+    const size_t hist_bytes = static_cast<size_t>(A.m) * sizeof(int);
+    const size_t stage_bytes = static_cast<size_t>(kRepackWaves) * 64 * D * sizeof(int);
+    const int lds_hist = repack_lds_hist(A.m, D) ? 1 : 0;
+    if (!lds_hist && (!A.partial || !A.blk)) return hipErrorInvalidValue;  // the layout has no partial counts
+    if (!lds_hist) {
+        // the degrees are written whole by the reduction
+        hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, A.bad_input, int64_t(1));
+    } else if (A.bad_input > A.deg) {
         hipLaunchKernelGGL(zero_ints, dim3(256), dim3(256), 0, s, A.deg, static_cast<int64_t>(A.bad_input - A.deg) + 1);
     } else {
         hipLaunchKernelGGL(zero_ints, dim3(256), dim3(256), 0, s, A.deg, static_cast<int64_t>(A.m));
         hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, A.bad_input, int64_t(1));
     }
-    const size_t hist_bytes = static_cast<size_t>(A.m) * sizeof(int);
-    const size_t stage_bytes = static_cast<size_t>(kRepackWaves) * 64 * D * sizeof(int);
-    const int lds_hist = repack_lds_hist(A.m, D) ? 1 : 0;
-    if (!lds_hist && !A.partial) return hipErrorInvalidValue;  // the layout has no partial counts
     const size_t lds = (lds_hist ? hist_bytes : 0) + stage_bytes;
     const void* fn = A.rows16 ? (lds_hist ? reinterpret_cast<const void*>(&repack_kernel<D, uint16_t, true>)
                                            : reinterpret_cast<const void*>(&repack_kernel<D, uint16_t, false>))
@@ -1142,9 +1207,13 @@ hipError_t prepare_d(const int32_t* col_idx, const MatrixView& A, hipStream_t s,
         if (e != hipSuccess) return e;
         int64_t nd = A.n * D;
         void* pargs[] = {const_cast<int32_t**>(&col_idx), const_cast<MatrixView*>(&A), &nd};
-        e = hipLaunchKernel(pf, dim3(static_cast<unsigned>(A.slices)), dim3(1024), pargs, plds, s);
+        const unsigned ranges = static_cast<unsigned>((A.m + kDegRange - 1) / kDegRange);
+        e = hipLaunchKernel(pf, dim3(static_cast<unsigned>(A.slices), ranges), dim3(1024), pargs, plds, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(deg_reduce_kernel, dim3(static_cast<unsigned>((A.m + 255) / 256)), dim3(256), 0, s, A);
+        const unsigned nblk = static_cast<unsigned>(deg_blocks(A.m));
+        hipLaunchKernelGGL(deg_reduce_kernel, dim3(nblk), dim3(1024), 0, s, A);
+        hipLaunchKernelGGL(scan_blocks_kernel, dim3(nblk), dim3(1024), 0, s, A, clear.p, clear.count);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, A, clear.p, clear.count);
     return hipGetLastError();
