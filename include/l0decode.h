@@ -125,7 +125,9 @@ typedef struct {
     int64_t* timeline;     /* device int64[6*max_iter + 16] or NULL: device wall-clock ticks
                               (hipDeviceAttributeWallClockRate) seen by workgroup 0: entry 0
                               at kernel start, entry 3*max_iter+7 once every workgroup has
-                              started, entry e after the e-th grid-wide barrier;
+                              started, entry e after the e-th grid-wide barrier
+                              for e <= 3*max_iter+6 (later ones, which only a
+                              shifted rule's empty passes reach, are not kept);
                               entries 3*max_iter+8+3*l+{0,1,2} when the vote of iteration l
                               has staged the residual, streamed all columns, and scored the
                               columns that passed the filter */

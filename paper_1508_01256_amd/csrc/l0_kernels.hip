@@ -69,6 +69,7 @@ struct BarrierSite {
     unsigned nx;      // members on that XCD
     unsigned nxcc;    // XCDs with at least one member
     unsigned epoch;   // barriers passed
+    unsigned tl_epochs;  // barriers whose exit the timeline records (its barrier part)
 };
 
 constexpr unsigned kClosed = 0x80000000u;  // admission closed (Ctrl::admit)
@@ -196,7 +197,8 @@ __device__ bool grid_sync(Ctrl* c, BarrierSite& b, uint64_t limit, int64_t* time
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         s_ok = ok;
-        if (timeline && b.member == 0) timeline[b.epoch] = static_cast<int64_t>(wall_clock64());
+        if (timeline && b.member == 0 && b.epoch < b.tl_epochs)
+            timeline[b.epoch] = static_cast<int64_t>(wall_clock64());
     }
     __syncthreads();
     return s_ok != 0;
@@ -596,6 +598,9 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     BarrierSite site;
     Registration reg;
     if (!admit_register(c, site, reg, adm.cap, p.timeline)) return;  // turned away: the members do the work
+    // the timeline's barrier part: entries 1 .. 3*max_iter + 6 (a shifted
+    // rule's empty passes can pass more barriers; those are not recorded)
+    site.tl_epochs = 3 * static_cast<unsigned>(p.max_iter) + 7;
 
     // Without a resume vector and with 32-bit words in LDS (y then has at
     // most 36864 entries), every workgroup derives max |y|, tau, ||y||_0 and

@@ -102,3 +102,56 @@ def test_shifted_rules():
             r = solve_into(A, y, 4, x, rule=rule)
         assert r["outcome"] == o["outcome"] and r["iters"] == o["iters"]
         assert np.array_equal(x.cpu().numpy().view(np.int64), o["x"].view(np.int64))
+
+
+def one_shot_into(inst, col, y, x, max_iter=100):
+    """l0_decode_ex into x (the one-shot decode); returns the result record."""
+    res = l0.new_result()
+    ws = torch.empty(l0.l0_workspace_bytes(inst.n, inst.m, inst.d, max_iter), dtype=torch.uint8, device="cuda")
+    assert l0.l0_decode_ex(col, inst.n, inst.m, inst.d, y, 4, max_iter, 1e-10, x, None, res, ws) == l0.L0_OK
+    torch.cuda.synchronize()
+    return l0.results_list(res.view(1, 3))[0]
+
+
+@pytest.mark.parametrize("offset", [0, 1])
+@pytest.mark.parametrize("n,m,k", SHAPES[:5])
+def test_one_shot_output_fully_written(n, m, k, offset):
+    """The one-shot decode (x_hat cleared during the first vote for 16-byte
+    aligned outputs, during the start-up otherwise) over NaN-filled outputs."""
+    inst = gen.make_instance(4500 + n % 89, n, m, 7, k)
+    say("one-shot clear", n, m, k, "offset", offset)
+    col = to_dev(inst.col_idx, torch.int32)
+    y = to_dev(inst.y, torch.float64)
+    o = oracle_run(n, m, 7, inst.col_idx, inst.y, 4)
+    for rep in range(2):
+        x = nan_buffer(n, offset)
+        r = one_shot_into(inst, col, y, x)
+        xh = x.cpu().numpy()
+        assert r["outcome"] == o["outcome"] and r["iters"] == o["iters"], (n, offset, rep)
+        assert np.array_equal(xh.view(np.int64), o["x"].view(np.int64)), (n, offset, rep)
+
+
+def test_one_shot_paths_that_end_before_a_vote():
+    """y = 0 and max_iter = 0 through the one-shot decode: x_hat all zero;
+    with an index out of range or a repeated row the input error wins."""
+    n, m = 128 * 33 + 1, 500
+    inst = gen.make_instance(4600, n, m, 7, 30)
+    col = to_dev(inst.col_idx, torch.int32)
+    zero_y = torch.zeros(m, dtype=torch.float64, device="cuda")
+    x = nan_buffer(n, 0)
+    r = one_shot_into(inst, col, zero_y, x)
+    assert r["outcome"] == l0.L0_CONVERGED and r["iters"] == 0 and not torch.any(x != 0).item()
+    x = nan_buffer(n, 0)
+    r = one_shot_into(inst, col, to_dev(inst.y, torch.float64), x, max_iter=0)
+    assert r["outcome"] == l0.L0_MAX_ITER and r["iters"] == 0 and not torch.any(x != 0).item()
+    bad = inst.col_idx.copy()
+    bad[11] = m
+    for yy in (zero_y, to_dev(inst.y, torch.float64)):
+        x = nan_buffer(n, 0)
+        r = one_shot_into(inst, to_dev(bad, torch.int32), yy, x)
+        assert r["outcome"] == l0.L0_DEV_BAD_INDEX and not torch.any(x != 0).item()
+    rep = inst.col_idx.copy()
+    rep[7 * 5 + 3] = rep[7 * 5 + 1]
+    x = nan_buffer(n, 0)
+    r = one_shot_into(inst, to_dev(rep, torch.int32), to_dev(inst.y, torch.float64), x)
+    assert r["outcome"] == l0.L0_DEV_REPEATED_ROW and not torch.any(x != 0).item()
