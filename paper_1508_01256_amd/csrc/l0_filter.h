@@ -173,9 +173,16 @@ struct Levels {
 };
 
 L0_HD void full_add(uint32_t a, uint32_t b, uint32_t c, uint32_t& s, uint32_t& cy) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    // one three-input bitwise instruction each (truth tables: parity 0x96,
+    // majority 0xE8)
+    s = __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+    cy = __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+#else
     const uint32_t x = a ^ b;
     s = x ^ c;
     cy = (x & c) | (~x & a);
+#endif
 }
 
 template <int D>
@@ -232,17 +239,26 @@ L0_HD bool bucket_filter(const uint32_t (&w)[D], int a, int rule) {
 #pragma unroll
     for (int k = 0; k < L; ++k) z |= static_cast<int>(c[k] >> 31) << k;
     const int need = a + (rule_counts_zeros(rule) ? z : 0);
-    // need > D can never be met; tested without a branch (the comparison
-    // below only sees need's low L bits then, and its result is discarded)
+    // need > D can never be met; tested without a branch (the carry chain
+    // below then sees a wrapped constant, and its result is discarded)
     const bool reachable = need <= D;
-    uint32_t ge = 0u, eq = 0xFFFFFFFFu;
+    // count >= need exactly when count + (2^L - need) carries out of L bits
+    // (for 1 <= need <= D < 2^L the constant lies in [1, 2^L)): the carry
+    // chain of that addition on the bit-sliced counts, one majority per level
+    const int K = (1 << L) - need;
+    // bit k of K as an all-ones or all-zero mask
+    auto kmask = [K](int k) { return static_cast<uint32_t>(-((K >> k) & 1)); };
+    uint32_t carry = c[0] & kmask(0);
 #pragma unroll
-    for (int k = L - 1; k >= 0; --k) {
-        const uint32_t tb = ((need >> k) & 1) ? 0xFFFFFFFFu : 0u;
-        ge |= eq & c[k] & ~tb;
-        eq &= ~(c[k] ^ tb);
+    for (int k = 1; k < L; ++k) {
+#if defined(__HIP_DEVICE_COMPILE__)
+        carry = __builtin_amdgcn_bitop3_b32(c[k], carry, kmask(k), 0xE8);  // majority
+#else
+        const uint32_t kb = kmask(k);
+        carry = (c[k] & carry) | (kb & (c[k] | carry));
+#endif
     }
-    return reachable & (((ge | eq) & kBucketBits) != 0u);
+    return reachable & ((carry & kBucketBits) != 0u);
 }
 
 
