@@ -887,7 +887,10 @@ __global__ void __launch_bounds__(1024) repack_kernel(const int32_t* col_idx, Ma
     __syncthreads();
     const int64_t nd = A.n * D;
     const int64_t ngroups = A.ntiles * (kTile / 64);
-    const int64_t wave = static_cast<int64_t>(blockIdx.x) * kRepackWaves + (threadIdx.x >> 6);
+    // the wave index is uniform across the wave: a scalar loop (no exec mask,
+    // scalar addresses)
+    const int64_t wave = static_cast<int64_t>(blockIdx.x) * kRepackWaves +
+                         __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kRepackWaves * G;
     const unsigned m = static_cast<unsigned>(A.m);
     int bad = 0;
