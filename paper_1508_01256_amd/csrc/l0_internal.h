@@ -119,7 +119,7 @@ __host__ __device__ inline bool weight_ok(double w) { return w > 0.0 && w <= 1.7
 constexpr int kMaxXcc = 16;     // XCDs (accelerator complex dies) a device may have
 constexpr int kXccStride = 32;  // per-XCD counters sit 128 bytes apart
 struct Ctrl {
-    unsigned int bar;        // grid barrier: arrivals of per-XCD leaders (monotonic)
+    unsigned int bar;        // grid barrier: arrivals of each XCD's last arriver (monotonic)
     int abort;               // set when a barrier timed out
     int err;                 // device-detected input errors (kErr* bits), 0 if none
     int nnz;                 // running ||r||_0
@@ -133,7 +133,6 @@ struct Ctrl {
     int pad[21];
     unsigned int xcount[kMaxXcc];                 // workgroups resident on each XCD
     unsigned int xarrive[kMaxXcc * kXccStride];   // per-XCD barrier arrivals (monotonic)
-    unsigned int xrelease[kMaxXcc * kXccStride];  // per-XCD release epoch
 };
 
 struct SolveBuffers {

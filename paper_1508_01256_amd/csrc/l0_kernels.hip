@@ -168,35 +168,38 @@ __device__ int admit_complete(Ctrl* c, BarrierSite& b, const Registration& reg, 
 }
 
 // Grid barrier, hierarchical over XCDs.  Each workgroup drains its own memory
-// operations (so its stores sit in its XCD's L2) and arrives on its XCD's
-// counter.  The last arriver of each XCD writes that L2 back once (agent-scope
-// release), arrives on the grid counter, waits for every XCD, invalidates its
-// caches (agent-scope acquire) and releases its XCD; the other workgroups wait
-// for that and acquire.  One L2 writeback per XCD instead of one per
-// workgroup; polling uses relaxed loads, which leave the L2 alone.  A wait
-// longer than `limit` raises the abort flag and every workgroup leaves the
-// kernel.  With a timeline, workgroup 0 stamps the wall clock.
+// operations (its stores then sit in its XCD's L2), invalidates its CU's L1
+// and arrives on its XCD's counter.  The last arriver of each XCD writes that
+// L2 back (agent-scope release), invalidates it, and arrives on the grid
+// counter; every workgroup then polls the grid counter with relaxed loads,
+// which leave the caches alone.  Why the invalidations may come before the
+// barrier completes: from its arrival until the grid counter is complete a
+// workgroup loads no data (thread 0 only touches the barrier words, the
+// other threads wait at the workgroup barrier), and the XCD's last arriver
+// invalidates the L2 only once every workgroup of its XCD has arrived; so
+// no line can enter either cache between its invalidation and the
+// completion, which follows every XCD's writeback.  Loads after the barrier
+// therefore miss on anything written elsewhere and read it from memory.
+// One L2 writeback and one L2 invalidation per XCD, one hop of waiting.  A
+// wait longer than `limit` raises the abort flag and every workgroup leaves
+// the kernel.  With a timeline, workgroup 0 stamps the wall clock.
 __device__ bool grid_sync(Ctrl* c, BarrierSite& b, uint64_t limit, int64_t* timeline = nullptr) {
     __shared__ int s_ok;
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this thread's loads and stores are done
     __syncthreads();
     b.epoch += 1;
     if (threadIdx.x == 0) {
-        int ok = 1;
+        // this CU's L1 (vector data cache); the wait covers the invalidation
+        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
         unsigned* xa = &c->xarrive[b.xcc * kXccStride];
-        unsigned* xr = &c->xrelease[b.xcc * kXccStride];
         const unsigned old = __hip_atomic_fetch_add(xa, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old + 1 == b.epoch * b.nx) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // L2 writeback, waited for
+            // the XCD's L2 (and this CU's L1), complete before the arrival
+            asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
             __hip_atomic_fetch_add(&c->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = wait_at_least(&c->bar, b.epoch * b.nxcc, c, limit) ? 1 : 0;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            __hip_atomic_store(xr, b.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            ok = wait_at_least(xr, b.epoch, c, limit) ? 1 : 0;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        s_ok = ok;
+        s_ok = wait_at_least(&c->bar, b.epoch * b.nxcc, c, limit) ? 1 : 0;
         if (timeline && b.member == 0 && b.epoch < b.tl_epochs)
             timeline[b.epoch] = static_cast<int64_t>(wall_clock64());
     }
