@@ -87,27 +87,34 @@ L0_HD bool exact_score_shifted(const double (&v)[D], int t, double tau, int rule
 // ---------------------------------------------------------------------------
 //
 // Each row i carries a 32-bit word: bit 31 marks a zero entry (|r_i| <= tau);
-// bits 0..30 are hashed buckets of the value r_i on a grid of width W, a power
-// of two with W >= 16 tau.  A row also marks the neighbouring bucket when r_i
-// lies within W/8 of a bucket edge.  If |r_u - r_t| <= tau (up to one
-// rounding), then r_u and r_t are either in one bucket or straddle an edge
-// within tau <= W/16 of both, so r_u carries the bucket bit of r_t.  Hence for
-// any candidate t, the number of the column's words holding t's bucket bit is
-// at least c_t, and a column can only be selected when some bucket bit is set
-// in at least a + z of its words (a for the frequency rule).  Columns passing
-// that test are scored exactly by exact_score() on FP64 values.
+// bits 0..30 mark buckets of the value r_i on a grid of width W, a power of
+// two with W >= 16 tau, bucket b taking bit (b mod 31).  A row also marks the
+// neighbouring bucket when r_i lies within W/8 of a bucket edge.  If
+// |r_u - r_t| <= tau (up to one rounding), then r_u and r_t are either in one
+// bucket or straddle an edge within tau <= W/16 of both, so r_u carries the
+// bucket bit of r_t.  Hence for any candidate t, the number of the column's
+// words holding t's bucket bit is at least c_t, and a column can only be
+// selected when some bucket bit is set in at least a + z of its words (a for
+// the frequency rule).  Columns passing that test are scored exactly by
+// exact_score() on FP64 values.  Any function of b alone keeps the test
+// necessary; b mod 31 costs a few floating-point operations, gives adjacent
+// buckets adjacent bits (cyclically), and maps unrelated values to a bit
+// about uniformly.
 
 constexpr double kEdge = 0.125;  // W/8 band at each bucket edge
 constexpr uint32_t kZeroBit = 0x80000000u;
 constexpr uint32_t kBucketBits = 0x7FFFFFFFu;
 
-L0_HD uint32_t bucket_bit(double b) {
-    // b is an integer-valued double; +0.0 folds a negative zero.
-    uint64_t h = __builtin_bit_cast(uint64_t, b + 0.0);
-    h *= 0x9E3779B97F4A7C15ull;
-    h ^= h >> 29;
-    h *= 0xBF58476D1CE4E5B9ull;
-    return 1u << static_cast<uint32_t>((h >> 32) % 31u);
+// b mod 31 (in 0..30) of an integer-valued double b, |b| < 2^51.  The
+// quotient estimate is within one of floor(b / 31), the fused remainder is
+// exact (a small integer), and one correction either way makes it the
+// remainder.
+L0_HD uint32_t bucket_index(double b) {
+    const double t = std::floor(b * (1.0 / 31.0));
+    double r = std::fma(-31.0, t, b);
+    if (r < 0.0) r += 31.0;
+    if (r >= 31.0) r -= 31.0;
+    return static_cast<uint32_t>(r);
 }
 
 L0_HD uint32_t row_word(double r, double tau, double inv_w) {
@@ -116,9 +123,11 @@ L0_HD uint32_t row_word(double r, double tau, double inv_w) {
     if (!(std::fabs(q) < 0x1p51)) return w | kBucketBits;  // huge or non-finite: every bucket
     const double b = std::floor(q);
     const double f = q - b;      // exact, in [0, 1)
-    w |= bucket_bit(b);
-    if (f < kEdge) w |= bucket_bit(b - 1.0);
-    if (f > 1.0 - kEdge) w |= bucket_bit(b + 1.0);
+    const uint32_t k = bucket_index(b);
+    const uint32_t bit = 1u << k;
+    w |= bit;
+    if (f < kEdge) w |= k == 0u ? (1u << 30) : (bit >> 1);        // bucket b - 1
+    if (f > 1.0 - kEdge) w |= k == 30u ? 1u : (bit << 1);         // bucket b + 1
     return w;
 }
 

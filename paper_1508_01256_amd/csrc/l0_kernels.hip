@@ -183,8 +183,11 @@ __device__ int admit_complete(Ctrl* c, BarrierSite& b, const Registration& reg, 
 // One L2 writeback and one L2 invalidation per XCD, one hop of waiting.  A
 // wait longer than `limit` raises the abort flag and every workgroup leaves
 // the kernel.  With a timeline, workgroup 0 stamps the wall clock.
-__device__ bool grid_sync(Ctrl* c, BarrierSite& b, uint64_t limit, int64_t* timeline = nullptr) {
-    __shared__ int s_ok;
+// The barrier in two halves: grid_arrive, then grid_wait.  Between them a
+// workgroup may load only data that nothing writes during the solve (the
+// index store) and store only what no other workgroup touches before the next
+// barrier: then nothing it loads can be stale, and the argument above holds.
+__device__ void grid_arrive(Ctrl* c, BarrierSite& b) {
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this thread's loads and stores are done
     __syncthreads();
     b.epoch += 1;
@@ -199,12 +202,23 @@ __device__ bool grid_sync(Ctrl* c, BarrierSite& b, uint64_t limit, int64_t* time
             asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
             __hip_atomic_fetch_add(&c->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+    }
+}
+
+__device__ bool grid_wait(Ctrl* c, BarrierSite& b, uint64_t limit, int64_t* timeline) {
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
         s_ok = wait_at_least(&c->bar, b.epoch * b.nxcc, c, limit) ? 1 : 0;
         if (timeline && b.member == 0 && b.epoch < b.tl_epochs)
             timeline[b.epoch] = static_cast<int64_t>(wall_clock64());
     }
     __syncthreads();
     return s_ok != 0;
+}
+
+__device__ bool grid_sync(Ctrl* c, BarrierSite& b, uint64_t limit, int64_t* timeline = nullptr) {
+    grid_arrive(c, b);
+    return grid_wait(c, b, limit, timeline);
 }
 
 // Sum of an int over the workgroup; the result is valid in every thread.
@@ -368,7 +382,7 @@ __device__ __forceinline__ void load_chunk(const void* soa, uint32_t g, uint32_t
 // the passing ones to the workgroup's LDS queue.  Only LDS is written here:
 // once the queue is full, positions are clamped to its last slot and the
 // overflow flag is raised (the queue is then discarded and the workgroup's
-// chunks are filtered again, see vote_phase).
+// chunks are filtered again, see vote_score).
 template <int D>
 __device__ __forceinline__ void filter_and_queue(const SolveParams& p, const uint32_t (&w)[D], uint32_t j,
                                                  uint32_t n, uint32_t lane, int* q_items, int* q_count,
@@ -416,7 +430,7 @@ __device__ __forceinline__ void filter_chunk(const SolveParams& p, const void* w
 // buffer's range check, so every call issues exactly one store and the
 // waits for the index loads can count it.  With 16-bit rows a lane clears a
 // pair of columns; the range covers whole pairs (the last column of an odd
-// n is cleared apart, see vote_phase).  A chunk at or past n stores nothing.
+// n is cleared apart, see vote_stream).  A chunk at or past n stores nothing.
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit dwords (gfx9)
 constexpr int kStoreNt = 2;             // streaming (nt) store
 
@@ -439,25 +453,22 @@ __device__ __forceinline__ void clear_chunk_x(double* x, uint32_t g, uint32_t n,
     }
 }
 
-// Vote phase.  Each wave streams its chunks (g = wave, wave + stride, ...)
-// with two chunks' row indices in flight (two register buffers taking turns,
-// so no copy waits on a load), gathers the rows' bucket words and runs the
-// bucket filter.  Its only global stores are the first vote's x_hat clears,
-// each issued after the loads that the next wait covers, so every wait
-// still covers loads only.  Columns passing the filter are then scored exactly on the same
-// residual.  If the workgroup's queue overflowed, the queue is dropped and
-// the workgroup filters its chunks again, scoring each passing column at
-// once (slow, but only for inputs where the filter passes thousands of
-// columns per workgroup).  Chunks are assigned statically: handing them out
-// through atomic counters costs more than the imbalance it removes (a wave
-// cannot wait for a chunk's loads without also waiting for an older claim).
-// l: the iteration (update counters); pos: the position shifted rules try in
-// this pass; clear_x: also zero x_hat chunk by chunk (each column's x_hat is
-// then zero before its workgroup scores it: the clears are complete before
-// the workgroup barrier that precedes the scoring).
+// Vote, first half.  Each wave streams its chunks (g = wave, wave + stride,
+// ...) with two chunks' row indices in flight (two register buffers taking
+// turns, so no copy waits on a load), gathers the rows' bucket words, runs
+// the bucket filter and queues the passing columns in LDS.  It loads nothing
+// but the index store.  Its only global stores are the first vote's x_hat
+// clears, each issued after the loads that the next wait covers, so every
+// wait still covers loads only.  Chunks are assigned statically: handing
+// them out through atomic counters costs more than the imbalance it removes
+// (a wave cannot wait for a chunk's loads without also waiting for an older
+// claim).  l: the iteration (timeline); CLEAR: also zero x_hat chunk by
+// chunk (each column's x_hat is then zero before its workgroup scores it:
+// the clears are complete before the workgroup barrier that ends the
+// stream).
 template <int D, int WM, bool CLEAR>
-__device__ void vote_phase(const SolveParams& p, const SolveState& st, int l, double tau, const void* lds_w,
-                           int* q_items, int* q_count, int* q_ovf, int pos, unsigned member, unsigned members) {
+__device__ void vote_stream(const SolveParams& p, int l, const void* lds_w, int* q_items, int* q_count,
+                            int* q_ovf, unsigned member, unsigned members) {
     constexpr bool R16 = Words<WM>::kRows16;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t nchunks = static_cast<uint32_t>(p.ntiles) * Chunk<R16>::kPerTile;
@@ -515,12 +526,27 @@ __device__ void vote_phase(const SolveParams& p, const SolveState& st, int l, do
     __syncthreads();
     if (p.timeline && member == 0 && threadIdx.x == 0)
         p.timeline[3 * p.max_iter + 9 + 3 * l] = static_cast<int64_t>(wall_clock64());
+}
+
+// The exact scoring of the columns the workgroup's stream queued (see
+// vote_stream), or, if its queue overflowed, of every passing column of its
+// chunks, filtered again.
+template <int D, int WM>
+__device__ void vote_score(const SolveParams& p, const SolveState& st, int l, double tau, const void* lds_w,
+                           int* q_items, int* q_count, int* q_ovf, int pos, unsigned member, unsigned members) {
+    constexpr bool R16 = Words<WM>::kRows16;
     if (*q_ovf == 0) {
         const int cnt = *q_count;
         for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D, R16>(p, st, l, q_items[q], tau, pos);
     } else {
         // overflow: every chunk of this wave again, passing columns scored directly
         constexpr uint32_t kCols = Chunk<R16>::kCols;
+        const uint32_t lane = threadIdx.x & 63;
+        const uint32_t nchunks = static_cast<uint32_t>(p.ntiles) * Chunk<R16>::kPerTile;
+        const uint32_t n = static_cast<uint32_t>(p.n);
+        const void* words = Words<WM>::kLds ? lds_w : p.rword;
+        const uint32_t stride = __builtin_amdgcn_readfirstlane(members * kWaves);
+        const uint32_t first = __builtin_amdgcn_readfirstlane(member * kWaves + (threadIdx.x >> 6));
         for (uint32_t c = first; c < nchunks; c += stride) {
             uint32_t rows[D];
             load_chunk<D, R16>(p.soa, c, lane, rows);
@@ -612,41 +638,38 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     // start-up and the first vote, and the first pass stages nothing.
     const bool local_init = WM == kWordsLds32 && p.x_init == nullptr;
 
+    // with local_init every y value this thread needs sits in registers:
+    // m <= 36864 = kLocalRows * kBlock, loaded once (one memory latency, not
+    // one per pass)
+    constexpr int kLocalRows = 36;
+    static_assert(kLocalRows * kBlock * 4 >= kLdsWordBytes, "local start covers every 32-bit LDS word mode");
+    double yv[kLocalRows];
     double ymax = 0.0;
     int nnz = 0;
     if (local_init) {
         // max |y| over every row, in every workgroup (a maximum is exact in
         // any order, so all workgroups agree); non-finite y is reported by
         // the shares below
-        constexpr int U = 8;
+#pragma unroll
+        for (int u = 0; u < kLocalRows; ++u)
+            if (u * kBlock < p.m) yv[u] = p.y[min(u * kBlock + tid, p.m - 1)];
         double lmax = 0.0;
-        for (int base = 0; base < p.m; base += U * kBlock) {
-            double v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = p.y[min(base + u * kBlock + tid, p.m - 1)];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (isfinite(v[u])) lmax = fmax(lmax, fabs(v[u]));
-        }
+        for (int u = 0; u < kLocalRows; ++u)
+            if (u * kBlock < p.m && isfinite(yv[u])) lmax = fmax(lmax, fabs(yv[u]));
         ymax = block_max(lmax);
     }
     const double tau0 = (p.tol_mode == L0_TOL_RELATIVE) ? p.tol * ymax : p.tol;
     if (local_init) {
         // ||y||_0 and the bucket words of r = y, all of them into LDS
         const double iw = 1.0 / bucket_width(tau0, ymax);
-        constexpr int U = 8;
         int cnt = 0;
-        for (int base = 0; base < p.m; base += U * kBlock) {
-            double v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = p.y[min(base + u * kBlock + tid, p.m - 1)];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = base + u * kBlock + tid;
-                if (i < p.m) {
-                    lds_w[i] = row_word(v[u], tau0, iw);
-                    cnt += fabs(v[u]) > tau0;
-                }
+        for (int u = 0; u < kLocalRows; ++u) {
+            const int i = u * kBlock + tid;
+            if (u * kBlock < p.m && i < p.m) {
+                lds_w[i] = row_word(yv[u], tau0, iw);
+                cnt += fabs(yv[u]) > tau0;
             }
         }
         nnz = block_sum(cnt);
@@ -709,15 +732,25 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             if (mb) atomicOr(&c->err, mb);
         }
     }
-    if (!grid_sync(c, site, limit, p.timeline)) {
-        if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
-        return;
-    }
-    const int err = ld_relaxed(&c->err);
-    if (err) {
-        if (fuse_clear) zero_x(p, gtid, gsize);
-        if (gtid == 0) write_result(p, 0, error_outcome(err), 0, 0, 0);
-        return;
+    // With the local start, x_hat cleared by the first vote and a vote to
+    // come (nnz and max_iter are the same in every workgroup), the first
+    // vote's stream runs between the two halves of this barrier: it loads
+    // only the index store and stores only its own x_hat chunks.  The input
+    // errors are then read after the wait, before any scoring.
+    const bool split_first = local_init && fuse_clear && nnz != 0 && p.max_iter > 0;
+    if (split_first) {
+        grid_arrive(c, site);
+    } else {
+        if (!grid_sync(c, site, limit, p.timeline)) {
+            if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
+            return;
+        }
+        const int err = ld_relaxed(&c->err);
+        if (err) {
+            if (fuse_clear) zero_x(p, gtid, gsize);
+            if (gtid == 0) write_result(p, 0, error_outcome(err), 0, 0, 0);
+            return;
+        }
     }
     if (!local_init)
         ymax = __longlong_as_double(static_cast<long long>(
@@ -764,7 +797,7 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         // iteration only the rows it touched are refreshed
         if (Words<WM>::kLds) stage_words<WM>(p, lds_w);
     }
-    if (gtid == 0 && p.trace) p.trace[0] = nnz;
+    if (gtid == 0 && p.trace && !split_first) p.trace[0] = nnz;
 
     // Vote passes are counted apart from iterations: a shifted rule's pass
     // that selects nothing is followed by another (the next position) and
@@ -789,10 +822,24 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         if (p.timeline && site.member == 0 && tid == 0)
             p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
         if (pass == 0 && fuse_clear)
-            vote_phase<D, WM, true>(p, st, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member, site.count);
+            vote_stream<D, WM, true>(p, l, lds_w, q_items, &q_count, &q_ovf, site.member, site.count);
         else
-            vote_phase<D, WM, false>(p, st, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member,
-                                     site.count);
+            vote_stream<D, WM, false>(p, l, lds_w, q_items, &q_count, &q_ovf, site.member, site.count);
+        if (pass == 0 && split_first) {
+            // the first barrier's second half: every start-up share is done
+            if (!grid_wait(c, site, limit, p.timeline)) {
+                if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
+                return;
+            }
+            const int err = ld_relaxed(&c->err);
+            if (err) {
+                // x_hat is zero: every workgroup has cleared its chunks
+                if (gtid == 0) write_result(p, 0, error_outcome(err), 0, 0, 0);
+                return;
+            }
+            if (gtid == 0 && p.trace) p.trace[0] = nnz;
+        }
+        vote_score<D, WM>(p, st, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member, site.count);
         if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
             return;

@@ -6,7 +6,10 @@
 //  4. the filter (on 32-bit words, and on words folded to 16 and to 8 bits)
 //     never rejects a column exact_score selects, on adversarial
 //     columns (clusters within tau, zeros, tiny values, values straddling
-//     bucket edges) for several tau, both rules and every threshold.
+//     bucket edges) for several tau, both rules and every threshold;
+//  5. bucket_index is the integer remainder mod 31 over the whole bucket
+//     range (|b| < 2^51): near multiples of 31, near the range's ends, near
+//     powers of two, and at random.
 // Exit status 0 and "OK" on success.
 #include <cstdio>
 #include <cstdlib>
@@ -193,9 +196,43 @@ static int check_exactness(int trials) {
     return 0;
 }
 
+static int check_bucket_index(int trials) {
+    std::vector<long long> bs = {0, 1, -1, 30, 31, 32, -30, -31, -32};
+    const long long top = (1LL << 51) - 1;
+    for (long long k = -3; k <= 3; ++k) {
+        bs.push_back(top + k - 3);
+        bs.push_back(-top - k + 3);
+    }
+    for (int e = 1; e < 51; ++e)
+        for (long long k = -2; k <= 2; ++k) {
+            bs.push_back((1LL << e) + k);
+            bs.push_back(-(1LL << e) + k);
+            // multiples of 31 near 2^e
+            const long long q = ((1LL << e) / 31) * 31;
+            bs.push_back(q + k);
+            bs.push_back(-q + k);
+        }
+    for (int i = 0; i < trials * 10; ++i) {
+        const int e = 1 + static_cast<int>(rng() % 50);
+        long long v = static_cast<long long>(rng() & ((1ULL << e) - 1));
+        bs.push_back(rng() & 1 ? v : -v);
+    }
+    for (long long b : bs) {
+        if (b > top || b < -top) continue;
+        const unsigned want = static_cast<unsigned>(((b % 31) + 31) % 31);
+        const unsigned got = bucket_index(static_cast<double>(b));
+        if (got != want) {
+            std::printf("bucket_index(%lld) = %u, want %u\n", b, got, want);
+            return 1;
+        }
+    }
+    if (bucket_index(-0.0) != 0u) { std::printf("bucket_index(-0.0)\n"); return 1; }
+    return 0;
+}
+
 int main(int argc, char** argv) {
     const int trials = argc > 1 ? std::atoi(argv[1]) : 20000;
-    int bad = 0;
+    int bad = check_bucket_index(trials);
     bad |= check_counts<2>(trials) | check_counts<3>(trials) | check_counts<5>(trials);
     bad |= check_counts<7>(trials) | check_counts<9>(trials) | check_counts<12>(trials);
     bad |= check_counts<16>(trials) | check_counts<20>(trials);
