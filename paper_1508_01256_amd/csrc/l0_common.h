@@ -41,40 +41,45 @@ __device__ __forceinline__ double column_update(const S& p, int64_t j, double v)
 // *tcount, enter j into the support (bitmap; on first entry append j to each
 // row's support list and count it in *support), and record every row it
 // touches once in the touched-row list (count in *affc).  S provides x,
-// member, slot_cnt, slots, row_off, aff_flag, aff_list.  The per-row atomics
-// are independent of each other and are issued together, so a selected
-// column costs a few memory round trips, not two per row.
+// member, slot_cnt, slots, row_off, aff_flag, aff_list.  Two rounds of
+// memory operations, each issued together: the support bit, the touched-row
+// flags, the rows' list offsets and x_hat_j; then, knowing which of these
+// are first, the list slots and the touched-row positions.
 template <int D, class S, class C>
 __device__ void apply_update(const S& p, C tcount, C support, C affc, int64_t j, double w,
                              const int (&rows)[D]) {
-    p.x[j] = p.x[j] + w;
+    const double x0 = p.x[j];
     fetch_add(tcount, 1);
     const uint32_t bit = 1u << (j & 31);
     const uint32_t old = __hip_atomic_fetch_or(&p.member[j >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int first[D];
+    int first[D], off[D];
 #pragma unroll
-    for (int t = 0; t < D; ++t)
+    for (int t = 0; t < D; ++t) {
         first[t] = __hip_atomic_exchange(&p.aff_flag[rows[t]], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((old & bit) == 0) {
-        fetch_add(support, 1);
-        int q[D], off[D];
-#pragma unroll
-        for (int t = 0; t < D; ++t) {
-            q[t] = fetch_add(&p.slot_cnt[rows[t]], 1);
-            off[t] = p.row_off[rows[t]];
-        }
-#pragma unroll
-        for (int t = 0; t < D; ++t) p.slots[off[t] + q[t]] = static_cast<int>(j);
+        off[t] = p.row_off[rows[t]];
     }
+    const bool fresh = (old & bit) == 0;
     int nfirst = 0;
 #pragma unroll
     for (int t = 0; t < D; ++t) nfirst += first[t] == 0;
+    int q[D];
+    if (fresh) {
+        fetch_add(support, 1);
+#pragma unroll
+        for (int t = 0; t < D; ++t) q[t] = fetch_add(&p.slot_cnt[rows[t]], 1);
+    }
+    int qa = 0;
+    if (nfirst) qa = fetch_add(affc, nfirst);
+    if (fresh) {
+#pragma unroll
+        for (int t = 0; t < D; ++t) p.slots[off[t] + q[t]] = static_cast<int>(j);
+    }
     if (nfirst) {
-        int q = fetch_add(affc, nfirst);
 #pragma unroll
         for (int t = 0; t < D; ++t)
-            if (first[t] == 0) p.aff_list[q++] = rows[t];
+            if (first[t] == 0) p.aff_list[qa++] = rows[t];
     }
+    p.x[j] = x0 + w;
 }
 
 // r_i = y_i - (sum over the support columns of row i, ascending, of their

@@ -168,32 +168,35 @@ __device__ int admit_complete(Ctrl* c, BarrierSite& b, const Registration& reg, 
 }
 
 // Grid barrier, hierarchical over XCDs.  Each workgroup drains its own memory
-// operations (its stores then sit in its XCD's L2), invalidates its CU's L1
-// and arrives on its XCD's counter.  The last arriver of each XCD writes that
-// L2 back (agent-scope release), invalidates it, and arrives on the grid
-// counter; every workgroup then polls the grid counter with relaxed loads,
-// which leave the caches alone.  Why the invalidations may come before the
-// barrier completes: from its arrival until the grid counter is complete a
-// workgroup loads no data (thread 0 only touches the barrier words, the
-// other threads wait at the workgroup barrier), and the XCD's last arriver
-// invalidates the L2 only once every workgroup of its XCD has arrived; so
-// no line can enter either cache between its invalidation and the
-// completion, which follows every XCD's writeback.  Loads after the barrier
-// therefore miss on anything written elsewhere and read it from memory.
-// One L2 writeback and one L2 invalidation per XCD, one hop of waiting.  A
-// wait longer than `limit` raises the abort flag and every workgroup leaves
-// the kernel.  With a timeline, workgroup 0 stamps the wall clock.
-// The barrier in two halves: grid_arrive, then grid_wait.  Between them a
-// workgroup may load only data that nothing writes during the solve (the
-// index store) and store only what no other workgroup touches before the next
-// barrier: then nothing it loads can be stale, and the argument above holds.
-__device__ void grid_arrive(Ctrl* c, BarrierSite& b) {
+// operations (its stores then sit in its XCD's L2: the vector L1 writes
+// through), invalidates its CU's L1 and arrives on its XCD's counter.  The
+// last arriver of each XCD writes that L2 back (agent-scope release),
+// invalidates it, and arrives on the grid counter; every workgroup then
+// polls the grid counter with relaxed loads, which leave the caches alone.
+// Why the invalidations may come before the barrier completes: from its
+// arrival until the grid counter is complete a workgroup loads no data
+// (thread 0 only touches the barrier words, the other threads wait at the
+// workgroup barrier), and the XCD's last arriver invalidates the L2 only
+// once every workgroup of its XCD has arrived; so no line can enter either
+// cache between its invalidation and the completion, which follows every
+// XCD's writeback.  Loads after the barrier therefore miss on anything
+// written elsewhere and read it from memory.  The L1 invalidation must be
+// agent-scope (it also invalidates the L2's non-coherent lines): a
+// workgroup-scope one leaves the L1's lines in place here, and decodes went
+// wrong with it (16 of 8192 small decodes, once the index loads were cached).
+// One hop of waiting, the invalidations off the critical path except the
+// last arriver's.  A wait longer than `limit` raises the abort flag and every
+// workgroup leaves the kernel.  With a timeline, workgroup 0 stamps the wall
+// clock.
+__device__ bool grid_sync(Ctrl* c, BarrierSite& b, uint64_t limit, int64_t* timeline = nullptr) {
+    __shared__ int s_ok;
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this thread's loads and stores are done
     __syncthreads();
     b.epoch += 1;
     if (threadIdx.x == 0) {
-        // this CU's L1 (vector data cache); the wait covers the invalidation
-        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+        // this CU's L1 (and the L2's non-coherent lines), agent scope; the
+        // wait covers the invalidation
+        asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
         unsigned* xa = &c->xarrive[b.xcc * kXccStride];
         const unsigned old = __hip_atomic_fetch_add(xa, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old + 1 == b.epoch * b.nx) {
@@ -202,23 +205,12 @@ __device__ void grid_arrive(Ctrl* c, BarrierSite& b) {
             asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
             __hip_atomic_fetch_add(&c->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-    }
-}
-
-__device__ bool grid_wait(Ctrl* c, BarrierSite& b, uint64_t limit, int64_t* timeline) {
-    __shared__ int s_ok;
-    if (threadIdx.x == 0) {
         s_ok = wait_at_least(&c->bar, b.epoch * b.nxcc, c, limit) ? 1 : 0;
         if (timeline && b.member == 0 && b.epoch < b.tl_epochs)
             timeline[b.epoch] = static_cast<int64_t>(wall_clock64());
     }
     __syncthreads();
     return s_ok != 0;
-}
-
-__device__ bool grid_sync(Ctrl* c, BarrierSite& b, uint64_t limit, int64_t* timeline = nullptr) {
-    grid_arrive(c, b);
-    return grid_wait(c, b, limit, timeline);
 }
 
 // Sum of an int over the workgroup; the result is valid in every thread.
@@ -367,7 +359,14 @@ struct Chunk {
     static constexpr uint32_t kPerTile = kTile / kCols;
 };
 
-template <int D, bool ROWS16>
+// Index loads of the vote's stream: streaming (nt) loads, or ordinary cached
+// loads when the index store is small enough to stay in the caches between
+// votes.  Measured per solve, nt against cached: n = 2^24 (235 MB store)
+// 181 vs 196 us, 2^23 (117 MB) 86.0 vs 86.5, 2^22 (59 MB) 82.4 vs 83.9,
+// 2^20 (29 MB, 32-bit rows) 190.5 vs 188.5.
+constexpr uint64_t kStreamNtBytes = 48ull << 20;
+
+template <int D, bool ROWS16, bool NT = true>
 __device__ __forceinline__ void load_chunk(const void* soa, uint32_t g, uint32_t lane, uint32_t (&rows)[D]) {
     constexpr uint32_t plane = ROWS16 ? kTile / 2 : kTile;  // 32-bit words per plane of a tile
     constexpr uint32_t per = Chunk<ROWS16>::kPerTile;
@@ -375,7 +374,10 @@ __device__ __forceinline__ void load_chunk(const void* soa, uint32_t g, uint32_t
     const uint32_t* __restrict__ q = static_cast<const uint32_t*>(soa) +
                                      (static_cast<uint64_t>(g / per) * (D * plane) + (g % per) * 64u + lane);
 #pragma unroll
-    for (int t = 0; t < D; ++t) rows[t] = __builtin_nontemporal_load(q + t * plane);
+    for (int t = 0; t < D; ++t) {
+        if constexpr (NT) rows[t] = __builtin_nontemporal_load(q + t * plane);
+        else rows[t] = q[t * plane];
+    }
 }
 
 // Filter the columns of one chunk (half a chunk for 16-bit rows) and append
@@ -423,50 +425,16 @@ __device__ __forceinline__ void filter_chunk(const SolveParams& p, const void* w
     }
 }
 
-// x_hat of chunk g's columns to zero (the first vote of a solve from x_hat =
-// 0 clears x_hat this way, beside the index loads).  x is 16-byte aligned
-// and g uniform over the wave.  The streaming store is a raw buffer store
-// over the chunk's columns below n: lanes past the end are dropped by the
-// buffer's range check, so every call issues exactly one store and the
-// waits for the index loads can count it.  With 16-bit rows a lane clears a
-// pair of columns; the range covers whole pairs (the last column of an odd
-// n is cleared apart, see vote_stream).  A chunk at or past n stores nothing.
-constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit dwords (gfx9)
-constexpr int kStoreNt = 2;             // streaming (nt) store
-
-template <bool R16>
-__device__ __forceinline__ void clear_chunk_x(double* x, uint32_t g, uint32_t n, uint32_t lane) {
-    constexpr uint32_t kCols = Chunk<R16>::kCols;
-    const uint32_t j0 = g * kCols;
-    uint32_t cols = j0 < n ? min(kCols, n - j0) : 0u;
-    if constexpr (R16) cols &= ~1u;
-    const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(x + (j0 < n ? j0 : 0u), 0, static_cast<int>(cols * 8),
-                                                        kRsrcWord3);
-    if constexpr (R16) {
-        typedef int int4v __attribute__((ext_vector_type(4)));
-        const int4v z = {0, 0, 0, 0};
-        __builtin_amdgcn_raw_buffer_store_b128(z, rsrc, static_cast<int>(lane * 16), 0, kStoreNt);
-    } else {
-        typedef int int2v __attribute__((ext_vector_type(2)));
-        const int2v z = {0, 0};
-        __builtin_amdgcn_raw_buffer_store_b64(z, rsrc, static_cast<int>(lane * 8), 0, kStoreNt);
-    }
-}
-
 // Vote, first half.  Each wave streams its chunks (g = wave, wave + stride,
 // ...) with two chunks' row indices in flight (two register buffers taking
 // turns, so no copy waits on a load), gathers the rows' bucket words, runs
 // the bucket filter and queues the passing columns in LDS.  It loads nothing
-// but the index store.  Its only global stores are the first vote's x_hat
-// clears, each issued after the loads that the next wait covers, so every
-// wait still covers loads only.  Chunks are assigned statically: handing
-// them out through atomic counters costs more than the imbalance it removes
-// (a wave cannot wait for a chunk's loads without also waiting for an older
-// claim).  l: the iteration (timeline); CLEAR: also zero x_hat chunk by
-// chunk (each column's x_hat is then zero before its workgroup scores it:
-// the clears are complete before the workgroup barrier that ends the
-// stream).
-template <int D, int WM, bool CLEAR>
+// but the index store and stores nothing to global memory, so every wait
+// covers loads only.  Chunks are assigned statically: handing them out
+// through atomic counters costs more than the imbalance it removes (a wave
+// cannot wait for a chunk's loads without also waiting for an older claim).
+// l: the iteration (timeline).
+template <int D, int WM, bool NT>
 __device__ void vote_stream(const SolveParams& p, int l, const void* lds_w, int* q_items, int* q_count,
                             int* q_ovf, unsigned member, unsigned members) {
     constexpr bool R16 = Words<WM>::kRows16;
@@ -482,46 +450,16 @@ __device__ void vote_stream(const SolveParams& p, int l, const void* lds_w, int*
     const uint32_t last = nchunks - 1;
     uint32_t g = first;
     uint32_t a[D], b[D];
-    if constexpr (!CLEAR) {
-        load_chunk<D, R16>(p.soa, min(g, last), lane, a);
-        load_chunk<D, R16>(p.soa, min(g + stride, last), lane, b);
-        while (g < nchunks) {
-            filter_chunk<D, WM>(p, words, a, g, n, lane, q_items, q_count, q_ovf);
-            load_chunk<D, R16>(p.soa, min(g + 2 * stride, last), lane, a);
-            g += stride;
-            if (g >= nchunks) break;
-            filter_chunk<D, WM>(p, words, b, g, n, lane, q_items, q_count, q_ovf);
-            load_chunk<D, R16>(p.soa, min(g + 2 * stride, last), lane, b);
-            g += stride;
-        }
-    } else {
-        // The same stream with a clear after each chunk, in whole pairs of
-        // chunks (a pair's second chunk past the end filters columns >= n,
-        // which never pass, and clears nothing): with no exit between the
-        // two halves every wait follows one fixed issue order, loads of one
-        // buffer, a store, loads of the other, and counts the store exactly
-        // (the store to nothing between the first loads of a and b keeps
-        // the first pass in that order).
-        load_chunk<D, R16>(p.soa, min(g, last), lane, a);
-        clear_chunk_x<R16>(p.x, nchunks, n, lane);
-        load_chunk<D, R16>(p.soa, min(g + stride, last), lane, b);
-        while (g < nchunks) {
-            filter_chunk<D, WM>(p, words, a, g, n, lane, q_items, q_count, q_ovf);
-            clear_chunk_x<R16>(p.x, g, n, lane);
-            load_chunk<D, R16>(p.soa, min(g + 2 * stride, last), lane, a);
-            filter_chunk<D, WM>(p, words, b, g + stride, n, lane, q_items, q_count, q_ovf);
-            clear_chunk_x<R16>(p.x, g + stride, n, lane);
-            load_chunk<D, R16>(p.soa, min(g + 3 * stride, last), lane, b);
-            g += 2 * stride;
-        }
-        if constexpr (R16) {
-            // the last column of an odd n, by the wave owning its chunk
-            const uint32_t cl = (n - 1) / Chunk<true>::kCols;
-            if ((n & 1) && cl >= first && (cl - first) % stride == 0 && lane == 0) p.x[n - 1] = 0.0;
-        }
-        // the clears are done (written to L2) before any wave of the
-        // workgroup scores a column, which reads and writes its x_hat
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    load_chunk<D, R16, NT>(p.soa, min(g, last), lane, a);
+    load_chunk<D, R16, NT>(p.soa, min(g + stride, last), lane, b);
+    while (g < nchunks) {
+        filter_chunk<D, WM>(p, words, a, g, n, lane, q_items, q_count, q_ovf);
+        load_chunk<D, R16, NT>(p.soa, min(g + 2 * stride, last), lane, a);
+        g += stride;
+        if (g >= nchunks) break;
+        filter_chunk<D, WM>(p, words, b, g, n, lane, q_items, q_count, q_ovf);
+        load_chunk<D, R16, NT>(p.soa, min(g + 2 * stride, last), lane, b);
+        g += stride;
     }
     __syncthreads();
     if (p.timeline && member == 0 && threadIdx.x == 0)
@@ -599,9 +537,33 @@ __device__ void stage_words(const SolveParams& p, void* lds_w) {
 // the persistent solve kernel
 // ---------------------------------------------------------------------------
 
-// x_hat = 0 over the grid (a solve from zero that ends before its first vote).
-__device__ void zero_x(const SolveParams& p, int64_t gtid, int64_t gsize) {
-    for (int64_t j = gtid; j < p.n; j += gsize) p.x[j] = 0.0;
+// x_hat = 0, this member's share: the members split x_hat into contiguous
+// runs written by plain 16-byte stores (a double before the first 16-byte
+// boundary and an odd last one apart; an x not 8-byte aligned by plain
+// 8-byte stores).  Measured in the n = 2^24 solve, against the same stores
+// striding over the grid and against streaming (nt) stores either way, this
+// form was the fastest by 2-10 us: the dirty lines it leaves in L2 drain
+// under the first vote.  Nothing here waits for the stores.
+__device__ void clear_x_share(double* x, int64_t n, unsigned member, unsigned count) {
+    typedef double double2v __attribute__((ext_vector_type(2)));
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(x);
+    if (addr & 7) {
+        const int64_t per = (n + count - 1) / count;
+        const int64_t j0 = per * member, j1 = min(j0 + per, n);
+        for (int64_t j = j0 + threadIdx.x; j < j1; j += kBlock) x[j] = 0.0;
+        return;
+    }
+    const int64_t head = (addr & 15) && n > 0 ? 1 : 0;
+    const int64_t pairs = (n - head) / 2;
+    const int64_t per = (pairs + count - 1) / count;
+    const int64_t q0 = per * member, q1 = min(q0 + per, pairs);
+    double2v* xp = reinterpret_cast<double2v*>(x + head);
+    const double2v z = {0.0, 0.0};
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) xp[q] = z;
+    if (member == 0 && threadIdx.x == 0) {
+        if (head) x[0] = 0.0;
+        if ((n - head) & 1) x[n - 1] = 0.0;
+    }
 }
 
 // Waves per SIMD the compiler must allow: one resident workgroup per CU (4
@@ -633,9 +595,9 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
 
     // Without a resume vector and with 32-bit words in LDS (y then has at
     // most 36864 entries), every workgroup derives max |y|, tau, ||y||_0 and
-    // all bucket words of r = y from y itself, during the launch ramp (it
-    // needs no other member): no grid barrier is needed between the
-    // start-up and the first vote, and the first pass stages nothing.
+    // all bucket words of r = y from y itself (it needs no other member): no
+    // grid barrier is needed between the start-up and the first vote, and
+    // the first pass stages nothing.
     const bool local_init = WM == kWordsLds32 && p.x_init == nullptr;
 
     // with local_init every y value this thread needs sits in registers:
@@ -648,8 +610,8 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     int nnz = 0;
     if (local_init) {
         // max |y| over every row, in every workgroup (a maximum is exact in
-        // any order, so all workgroups agree); non-finite y is reported by
-        // the shares below
+        // any order, so all workgroups agree), during the launch ramp;
+        // non-finite y is reported by the shares below
 #pragma unroll
         for (int u = 0; u < kLocalRows; ++u)
             if (u * kBlock < p.m) yv[u] = p.y[min(u * kBlock + tid, p.m - 1)];
@@ -659,6 +621,22 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             if (u * kBlock < p.m && isfinite(yv[u])) lmax = fmax(lmax, fabs(yv[u]));
         ymax = block_max(lmax);
     }
+
+    // the member count and the barrier sites; work is split by member id
+    const int state = admit_complete(c, site, reg, adm.window, limit);
+    const int64_t gtid = static_cast<int64_t>(site.member) * kBlock + tid;
+    const int64_t gsize = static_cast<int64_t>(site.count) * kBlock;
+    if (state < 0) {
+        if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
+        return;
+    }
+    if (p.timeline && site.member == 0 && tid == 0)
+        p.timeline[3 * p.max_iter + 7] = static_cast<int64_t>(wall_clock64());
+    // x_hat = 0 for a solve from zero, a pure write stream: issued before
+    // the word arithmetic below, which loads nothing, so the stores drain
+    // under it (mixed with the first vote's index stream they cost more
+    // than alone)
+    if (p.x_init == nullptr) clear_x_share(p.x, p.n, site.member, site.count);
     const double tau0 = (p.tol_mode == L0_TOL_RELATIVE) ? p.tol * ymax : p.tol;
     if (local_init) {
         // ||y||_0 and the bucket words of r = y, all of them into LDS
@@ -673,35 +651,16 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             }
         }
         nnz = block_sum(cnt);
-    }
-
-    // the member count and the barrier sites; work is split by member id
-    const int state = admit_complete(c, site, reg, adm.window, limit);
-    const int64_t gtid = static_cast<int64_t>(site.member) * kBlock + tid;
-    const int64_t gsize = static_cast<int64_t>(site.count) * kBlock;
-    if (state < 0) {
-        if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
-        return;
-    }
-    if (p.timeline && site.member == 0 && tid == 0)
-        p.timeline[3 * p.max_iter + 7] = static_cast<int64_t>(wall_clock64());
-    if (local_init) {
         // this workgroup's share of the words to the global word array
         for (int64_t i = gtid; i < p.m; i += gsize) static_cast<uint32_t*>(p.rword)[i] = lds_w[i];
         if (gtid == 0) __hip_atomic_store(&c->nnz, nnz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    // --- init: x_hat (a resume copies x_init; from zero, the first vote
-    //     clears a 16-byte aligned x_hat as it streams the index store),
-    //     support bitmap, per-row state, max |y|, finiteness of y, usable
-    //     column weights
-    const bool fuse_clear = p.x_init == nullptr && (reinterpret_cast<uintptr_t>(p.x) & 15) == 0;
+    // --- init: x_hat of a resume (copied from x_init), support bitmap,
+    //     per-row state, max |y|, finiteness of y, usable column weights
     {
         int bad_w = 0;
-        if (p.x_init) {
+        if (p.x_init)
             for (int64_t j = gtid; j < p.n; j += gsize) p.x[j] = p.x_init[j];
-        } else if (!fuse_clear) {
-            for (int64_t j = gtid; j < p.n; j += gsize) p.x[j] = 0.0;
-        }
         if (p.w)
             for (int64_t j = gtid; j < p.n; j += gsize)
                 if (!weight_ok(p.w[j])) bad_w = 1;
@@ -720,9 +679,10 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             if (local_init) p.r[i] = yi;
         }
         if (!local_init) {
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
-            if ((tid & 63) == 0 && lmax > 0.0)
+            // one atomic per workgroup (atomics on one address are served
+            // one at a time)
+            lmax = block_max(lmax);
+            if (tid == 0 && lmax > 0.0)
                 atomicMax(reinterpret_cast<unsigned long long*>(&c->maxabs_bits),
                           static_cast<unsigned long long>(__double_as_longlong(lmax)));
         }
@@ -732,25 +692,15 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             if (mb) atomicOr(&c->err, mb);
         }
     }
-    // With the local start, x_hat cleared by the first vote and a vote to
-    // come (nnz and max_iter are the same in every workgroup), the first
-    // vote's stream runs between the two halves of this barrier: it loads
-    // only the index store and stores only its own x_hat chunks.  The input
-    // errors are then read after the wait, before any scoring.
-    const bool split_first = local_init && fuse_clear && nnz != 0 && p.max_iter > 0;
-    if (split_first) {
-        grid_arrive(c, site);
-    } else {
-        if (!grid_sync(c, site, limit, p.timeline)) {
-            if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
-            return;
-        }
-        const int err = ld_relaxed(&c->err);
-        if (err) {
-            if (fuse_clear) zero_x(p, gtid, gsize);
-            if (gtid == 0) write_result(p, 0, error_outcome(err), 0, 0, 0);
-            return;
-        }
+    if (!grid_sync(c, site, limit, p.timeline)) {
+        if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
+        return;
+    }
+    const int err = ld_relaxed(&c->err);
+    if (err) {
+        // x_hat is zero already
+        if (gtid == 0) write_result(p, 0, error_outcome(err), 0, 0, 0);
+        return;
     }
     if (!local_init)
         ymax = __longlong_as_double(static_cast<long long>(
@@ -797,19 +747,18 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         // iteration only the rows it touched are refreshed
         if (Words<WM>::kLds) stage_words<WM>(p, lds_w);
     }
-    if (gtid == 0 && p.trace && !split_first) p.trace[0] = nnz;
+    if (gtid == 0 && p.trace) p.trace[0] = nnz;
 
     // Vote passes are counted apart from iterations: a shifted rule's pass
     // that selects nothing is followed by another (the next position) and
     // the run stalls after D such passes in a row.
     int l = 0, pass = 0, empty = 0;
     const bool shifted = rule_is_shifted(p.rule);
+    const bool stream_nt = static_cast<uint64_t>(p.ntiles) * D * kTile * (R16 ? 2 : 4) > kStreamNtBytes;
     int outcome;
     long long updates = 0;
     for (;;) {
         if (nnz == 0 || l == p.max_iter) {
-            // ended before any vote: x_hat (from zero) was not cleared yet
-            if (pass == 0 && fuse_clear) zero_x(p, gtid, gsize);
             outcome = nnz == 0 ? L0_CONVERGED : L0_MAX_ITER;
             break;
         }
@@ -821,24 +770,8 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         // iteration)
         if (p.timeline && site.member == 0 && tid == 0)
             p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
-        if (pass == 0 && fuse_clear)
-            vote_stream<D, WM, true>(p, l, lds_w, q_items, &q_count, &q_ovf, site.member, site.count);
-        else
-            vote_stream<D, WM, false>(p, l, lds_w, q_items, &q_count, &q_ovf, site.member, site.count);
-        if (pass == 0 && split_first) {
-            // the first barrier's second half: every start-up share is done
-            if (!grid_wait(c, site, limit, p.timeline)) {
-                if (gtid == 0) write_result(p, 0, L0_DEV_ABORTED, 0, 0, 0);
-                return;
-            }
-            const int err = ld_relaxed(&c->err);
-            if (err) {
-                // x_hat is zero: every workgroup has cleared its chunks
-                if (gtid == 0) write_result(p, 0, error_outcome(err), 0, 0, 0);
-                return;
-            }
-            if (gtid == 0 && p.trace) p.trace[0] = nnz;
-        }
+        if (stream_nt) vote_stream<D, WM, true>(p, l, lds_w, q_items, &q_count, &q_ovf, site.member, site.count);
+        else vote_stream<D, WM, false>(p, l, lds_w, q_items, &q_count, &q_ovf, site.member, site.count);
         vote_score<D, WM>(p, st, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member, site.count);
         if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);

@@ -1,10 +1,11 @@
 """A solve from x_hat = 0 leaves no value of the caller's output buffer
-behind.  The solve kernel zeroes x_hat during its first vote (one streaming
-store per chunk of columns, 16-byte aligned buffers) or during its start-up
-(other alignments); these tests fill the output with NaN first and compare
-every entry with the oracle, bitwise, across ragged sizes, both row widths,
-both alignments, and the paths that end before any vote (y = 0, max_iter = 0,
-a device-detected input error)."""
+behind.  The solve kernel zeroes x_hat during its start-up, each member a
+contiguous run of it by 16-byte stores (a leading double when the buffer is
+8 but not 16 bytes past an aligned address, an odd last one);
+these tests fill the output with NaN first and compare every entry with the
+oracle, bitwise, across ragged sizes, both row widths, both alignments, and
+the paths that end before any vote (y = 0, max_iter = 0, a device-detected
+input error)."""
 import numpy as np
 import pytest
 import torch
@@ -116,8 +117,7 @@ def one_shot_into(inst, col, y, x, max_iter=100):
 @pytest.mark.parametrize("offset", [0, 1])
 @pytest.mark.parametrize("n,m,k", SHAPES[:5])
 def test_one_shot_output_fully_written(n, m, k, offset):
-    """The one-shot decode (x_hat cleared during the first vote for 16-byte
-    aligned outputs, during the start-up otherwise) over NaN-filled outputs."""
+    """The one-shot decode over NaN-filled outputs, both alignments."""
     inst = gen.make_instance(4500 + n % 89, n, m, 7, k)
     say("one-shot clear", n, m, k, "offset", offset)
     col = to_dev(inst.col_idx, torch.int32)
@@ -155,3 +155,27 @@ def test_one_shot_paths_that_end_before_a_vote():
     x = nan_buffer(n, 0)
     r = one_shot_into(inst, to_dev(rep, torch.int32), to_dev(inst.y, torch.float64), x)
     assert r["outcome"] == l0.L0_DEV_REPEATED_ROW and not torch.any(x != 0).item()
+
+
+@pytest.mark.parametrize("cap", [1, 3, 7, 100])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_output_fully_written_with_few_members(cap, offset):
+    """The members split the clear into contiguous runs by their count: with
+    admission capped at 1, 3, 7 or 100 members (145 tiles: 10 workgroups
+    launched) every entry is still written."""
+    n, m, k = 256 * 144 + 77, 3700, 300
+    inst = gen.make_instance(4700 + cap, n, m, 7, k)
+    say("clear with members", cap, "offset", offset)
+    col = to_dev(inst.col_idx, torch.int32)
+    y = to_dev(inst.y, torch.float64)
+    o = oracle_run(n, m, 7, inst.col_idx, inst.y, 4)
+    l0.l0_set_solve_admission(cap, 0)
+    try:
+        with l0.Matrix(col, n, m, 7) as A:
+            x = nan_buffer(n, offset)
+            r = solve_into(A, y, 4, x)
+    finally:
+        l0.l0_set_solve_admission(0, 0)
+    xh = x.cpu().numpy()
+    assert r["outcome"] == o["outcome"] and r["iters"] == o["iters"], (cap, offset)
+    assert np.array_equal(xh.view(np.int64), o["x"].view(np.int64)), (cap, offset)
