@@ -318,6 +318,10 @@ def main():
         # the bytes the counters saw per launch, over the same launch time
         roofline["counter_gbs"] = round(traffic / (solve_avg * 1e-3) / 1e9, 1)
         roofline["counter_frac"] = round(traffic / (solve_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    if stored_launch < bytes_launch:
+        roofline["note"] = ("frac counts the method's 4-byte indices; the library streams "
+                            f"{8 * index_bytes(m)}-bit ones (stored_gbs), so frac can pass 1; "
+                            "counter_frac is the memory system's fraction")
     gx = xs.cpu().numpy()
     del xs, rs, x, res, ws, trace, tsize, tl
 

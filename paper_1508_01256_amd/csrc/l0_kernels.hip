@@ -537,6 +537,71 @@ __device__ void stage_words(const SolveParams& p, void* lds_w) {
 // the persistent solve kernel
 // ---------------------------------------------------------------------------
 
+// Residual rows whose support-list merge is long for one thread (the
+// insertion of the new entries into the sorted prefix moves about
+// new x count entries of global memory one at a time) go to the whole
+// workgroup, at most kHeavyRows per workgroup and pass; lists up to half the
+// queue's LDS.
+constexpr int kHeavyRows = 32;
+constexpr int kHeavyWork = 256;
+
+template <class S>
+__device__ __forceinline__ bool heavy_row(const S& st, int i) {
+    const int cnt = st.slot_cnt[i];
+    const int fresh = cnt - st.slot_sorted[i];
+    return cnt <= kQueue / 2 && fresh > 0 && fresh * cnt > kHeavyWork;
+}
+
+// row_residual for one row, by the whole workgroup (every thread calls it;
+// the result is valid in thread 0), buf: kQueue ints of LDS.  The list's
+// column ids are distinct, so entry v goes to position (entries below v):
+// one thread per entry counts them; the sorted list is written back; the
+// column terms are gathered 512 at a time into LDS and thread 0 adds them in
+// ascending j from +0.0 (the order and rounding of row_residual).
+template <class S>
+__device__ double wg_row_residual(const S& st, int i, int* buf) {
+    const int tid = threadIdx.x;
+    const int cnt = st.slot_cnt[i];
+    int* const list = st.slots + st.row_off[i];
+    int* const a = buf;
+    int* const b = buf + kQueue / 2;
+    for (int t = tid; t < cnt; t += kBlock) a[t] = list[t];
+    __syncthreads();
+    for (int t = tid; t < cnt; t += kBlock) {
+        const int v = a[t];
+        int below = 0;
+        for (int u = 0; u < cnt; ++u) below += a[u] < v;
+        b[below] = v;
+    }
+    __syncthreads();
+    for (int t = tid; t < cnt; t += kBlock) list[t] = b[t];
+    if (tid == 0) st.slot_sorted[i] = cnt;
+    double* const terms = reinterpret_cast<double*>(a);  // kQueue / 4 doubles
+    constexpr int kChunk = kQueue / 4;
+    double sum = 0.0;
+    for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+        const int len = min(kChunk, cnt - c0);
+        for (int t = tid; t < len; t += kBlock) terms[t] = column_term(st, b[c0 + t]);
+        __syncthreads();
+        if (tid == 0)
+            for (int t = 0; t < len; ++t) sum += terms[t];
+        __syncthreads();
+    }
+    return st.y[i] - sum;
+}
+
+// The new residual value rn of touched row i: r_i, its bucket word and its
+// touched flag; returns the change of ||r||_0.
+template <int WM>
+__device__ __forceinline__ int finish_row(const SolveParams& p, int i, double rn, double tau, double inv_w) {
+    const bool was = fabs(p.r[i]) > tau;
+    const bool now = fabs(rn) > tau;
+    p.r[i] = rn;
+    put_word<WM>(p.rword, static_cast<uint32_t>(i), row_word(rn, tau, inv_w));
+    p.aff_flag[i] = 0;
+    return static_cast<int>(now) - static_cast<int>(was);
+}
+
 // x_hat = 0, this member's share: the members split x_hat into contiguous
 // runs written by plain 16-byte stores (a double before the first 16-byte
 // boundary and an odd last one apart; an x not 8-byte aligned by plain
@@ -581,6 +646,8 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     extern __shared__ uint32_t lds_w[];
     __shared__ int q_items[kQueue];
     __shared__ int q_count, q_ovf;
+    __shared__ int h_rows[kHeavyRows];
+    __shared__ int h_count;
     constexpr bool R16 = Words<WM>::kRows16;
     if (threadIdx.x == 0) q_count = q_ovf = 0;
     const int tid = threadIdx.x;
@@ -786,23 +853,33 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         }
         empty = 0;
 
-        // residual update of the touched rows, ||r||_0 by its change
+        // residual update of the touched rows, ||r||_0 by its change; a row
+        // whose list merge would be long for one thread is handed to the
+        // whole workgroup (the queue's LDS is free here)
         const int na = ld_relaxed(&p.affc[l]);
         {
-            // Each pass of this grid-stride loop has lane 0 of the wave active
-            // whenever any lane is, so lane 0 accumulates the wave's change.
-            int wdelta = 0;
+            if (tid == 0) h_count = 0;
+            __syncthreads();
+            int delta = 0;
             for (int64_t q = gtid; q < na; q += gsize) {
                 const int i = st.aff_list[q];
-                const double rn = row_residual(st, i);
-                const bool was = fabs(p.r[i]) > tau;
-                const bool now = fabs(rn) > tau;
-                p.r[i] = rn;
-                put_word<WM>(p.rword, static_cast<uint32_t>(i), row_word(rn, tau, inv_w));
-                p.aff_flag[i] = 0;
-                wdelta += wave_count(now && !was) - wave_count(was && !now);
+                if (heavy_row(st, i)) {
+                    const int h = atomicAdd(&h_count, 1);
+                    if (h < kHeavyRows) {
+                        h_rows[h] = i;
+                        continue;
+                    }
+                }
+                delta += finish_row<WM>(p, i, row_residual(st, i), tau, inv_w);
             }
-            const int b = block_sum((tid & 63) == 0 ? wdelta : 0);
+            __syncthreads();
+            const int nh = min(h_count, kHeavyRows);
+            for (int h = 0; h < nh; ++h) {
+                const int i = h_rows[h];
+                const double rn = wg_row_residual(st, i, q_items);
+                if (tid == 0) delta += finish_row<WM>(p, i, rn, tau, inv_w);
+            }
+            const int b = block_sum(delta);
             if (tid == 0 && b) atomicAdd(&c->nnz, b);
         }
         if (!grid_sync(c, site, limit, p.timeline)) {
