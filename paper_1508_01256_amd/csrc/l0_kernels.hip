@@ -331,11 +331,74 @@ __device__ __forceinline__ SolveState state_of(const SolveParams& p, int l) {
 // the score of one column (eq. (selection_l0))
 // ---------------------------------------------------------------------------
 
+// A workgroup's updates of one vote, gathered in LDS so that the counters
+// every workgroup shares (updates, support size, touched-row list length) see
+// one atomic per workgroup, not one per update: atomics on one address are
+// served one at a time (1361 updates in the first vote at n = 2^20).
+// Touched rows wait in `rows` for their list positions; those that do not
+// fit are appended at once.
+constexpr int kAffBuf = 512;
+struct WgUpdates {
+    int t;     // updates
+    int s;     // columns entering the support
+    int a;     // touched rows reserved in `rows` (may pass kAffBuf)
+    int base;  // their first position in the touched-row list
+    int rows[kAffBuf];
+};
+
+// apply_update (l0_common.h) with the shared counters gathered in u: x_hat_j
+// += w, the support bit, the per-row support lists and the touched flags as
+// there; the count of updates and of new support columns in LDS; touched
+// rows into u->rows (the part past kAffBuf straight to the list).
+template <int D>
+__device__ void apply_update_wg(const SolveState& p, WgUpdates* u, int32_t* affc, int64_t j, double w,
+                                const int (&rows)[D]) {
+    const double x0 = p.x[j];
+    const uint32_t bit = 1u << (j & 31);
+    const uint32_t old = __hip_atomic_fetch_or(&p.member[j >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int first[D], off[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        first[t] = __hip_atomic_exchange(&p.aff_flag[rows[t]], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        off[t] = p.row_off[rows[t]];
+    }
+    atomicAdd(&u->t, 1);
+    const bool fresh = (old & bit) == 0;
+    int q[D];
+    if (fresh) {
+        atomicAdd(&u->s, 1);
+#pragma unroll
+        for (int t = 0; t < D; ++t) q[t] = fetch_add(&p.slot_cnt[rows[t]], 1);
+    }
+    int nfirst = 0;
+#pragma unroll
+    for (int t = 0; t < D; ++t) nfirst += first[t] == 0;
+    if (nfirst) {
+        const int k = atomicAdd(&u->a, nfirst);
+        const int nbuf = k < kAffBuf ? min(nfirst, kAffBuf - k) : 0;
+        int qa = nbuf < nfirst ? fetch_add(affc, nfirst - nbuf) : 0;
+        int e = 0;
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            if (first[t] != 0) continue;
+            if (e < nbuf) u->rows[k + e] = rows[t];
+            else p.aff_list[qa++] = rows[t];
+            ++e;
+        }
+    }
+    if (fresh) {
+#pragma unroll
+        for (int t = 0; t < D; ++t) p.slots[off[t] + q[t]] = static_cast<int>(j);
+    }
+    p.x[j] = x0 + w;
+}
+
 // Exact scoring of one column that passed the bucket filter: its rows come
 // from the repacked index store, its values from the FP64 residual.
 // (Shifted rules: the one candidate of this pass, at position pos.)
 template <int D, bool ROWS16>
-__device__ void score_exact(const SolveParams& p, const SolveState& st, int l, int64_t j, double tau, int pos) {
+__device__ void score_exact(const SolveParams& p, const SolveState& st, int l, int64_t j, double tau, int pos,
+                            WgUpdates* u) {
     int rows[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) rows[t] = soa_row<ROWS16>(p.soa, j, t, D);
@@ -345,7 +408,7 @@ __device__ void score_exact(const SolveParams& p, const SolveState& st, int l, i
     double om;
     const bool sel = rule_is_shifted(p.rule) ? exact_score_shifted<D>(v, pos, tau, p.rule, p.a, om)
                                              : exact_score<D>(v, tau, p.rule, p.a, om);
-    if (sel) apply_update<D>(st, &p.tcount[l], &p.ctrl->support, &p.affc[l], j, column_update(st, j, om), rows);
+    if (sel) apply_update_wg<D>(st, u, &p.affc[l], j, column_update(st, j, om), rows);
 }
 
 constexpr int kQueue = 2048;  // per-workgroup queue of columns passing the filter
@@ -471,11 +534,12 @@ __device__ void vote_stream(const SolveParams& p, int l, const void* lds_w, int*
 // chunks, filtered again.
 template <int D, int WM>
 __device__ void vote_score(const SolveParams& p, const SolveState& st, int l, double tau, const void* lds_w,
-                           int* q_items, int* q_count, int* q_ovf, int pos, unsigned member, unsigned members) {
+                           int* q_items, int* q_count, int* q_ovf, int pos, unsigned member, unsigned members,
+                           WgUpdates* u) {
     constexpr bool R16 = Words<WM>::kRows16;
     if (*q_ovf == 0) {
         const int cnt = *q_count;
-        for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D, R16>(p, st, l, q_items[q], tau, pos);
+        for (int q = threadIdx.x; q < cnt; q += kBlock) score_exact<D, R16>(p, st, l, q_items[q], tau, pos, u);
     } else {
         // overflow: every chunk of this wave again, passing columns scored directly
         constexpr uint32_t kCols = Chunk<R16>::kCols;
@@ -494,14 +558,26 @@ __device__ void vote_score(const SolveParams& p, const SolveState& st, int l, do
 #pragma unroll
                 for (int t = 0; t < D; ++t) w[t] = word_at<WM>(words, chunk_row<R16>(rows[t], h));
                 const uint32_t j = c * kCols + (R16 ? 2 * lane + h : lane);
-                if (bucket_filter<D>(w, p.a, p.rule) && j < n) score_exact<D, R16>(p, st, l, j, tau, pos);
+                if (bucket_filter<D>(w, p.a, p.rule) && j < n) score_exact<D, R16>(p, st, l, j, tau, pos, u);
             }
         }
     }
     __syncthreads();
+    // the workgroup's shares of the shared counters, one atomic each, and
+    // the positions of its buffered touched rows
+    const int nbuf = min(u->a, kAffBuf);
+    if (threadIdx.x == 0) {
+        if (u->t) fetch_add(&p.tcount[l], u->t);
+        if (u->s) fetch_add(&p.ctrl->support, u->s);
+        u->base = nbuf ? fetch_add(&p.affc[l], nbuf) : 0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nbuf; t += kBlock) st.aff_list[u->base + t] = u->rows[t];
+    __syncthreads();
     if (threadIdx.x == 0) {
         *q_count = 0;
         *q_ovf = 0;
+        u->t = u->s = u->a = 0;
         if (p.timeline && member == 0)
             p.timeline[3 * p.max_iter + 10 + 3 * l] = static_cast<int64_t>(wall_clock64());
     }
@@ -648,8 +724,12 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
     __shared__ int q_count, q_ovf;
     __shared__ int h_rows[kHeavyRows];
     __shared__ int h_count;
+    __shared__ WgUpdates wg_upd;
     constexpr bool R16 = Words<WM>::kRows16;
-    if (threadIdx.x == 0) q_count = q_ovf = 0;
+    if (threadIdx.x == 0) {
+        q_count = q_ovf = 0;
+        wg_upd.t = wg_upd.s = wg_upd.a = 0;
+    }
     const int tid = threadIdx.x;
     Ctrl* c = p.ctrl;
     const uint64_t limit = adm.limit;
@@ -839,7 +919,8 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             p.timeline[3 * p.max_iter + 8 + 3 * l] = static_cast<int64_t>(wall_clock64());
         if (stream_nt) vote_stream<D, WM, true>(p, l, lds_w, q_items, &q_count, &q_ovf, site.member, site.count);
         else vote_stream<D, WM, false>(p, l, lds_w, q_items, &q_count, &q_ovf, site.member, site.count);
-        vote_score<D, WM>(p, st, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member, site.count);
+        vote_score<D, WM>(p, st, l, tau, lds_w, q_items, &q_count, &q_ovf, pos, site.member, site.count,
+                          &wg_upd);
         if (!grid_sync(c, site, limit, p.timeline)) {
             if (gtid == 0) write_result(p, l, L0_DEV_ABORTED, nnz, 0, updates);
             return;
