@@ -942,7 +942,10 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
             if (tid == 0) h_count = 0;
             __syncthreads();
             int delta = 0;
-            for (int64_t q = gtid; q < na; q += gsize) {
+            // touched rows dealt round-robin over the workgroups (entry q to
+            // workgroup q mod count), so that a short list occupies every CU's
+            // memory pipeline instead of the first few workgroups'
+            for (int64_t q = static_cast<int64_t>(tid) * site.count + site.member; q < na; q += gsize) {
                 const int i = st.aff_list[q];
                 if (heavy_row(st, i)) {
                     const int h = atomicAdd(&h_count, 1);
