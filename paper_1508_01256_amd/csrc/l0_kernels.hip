@@ -977,13 +977,19 @@ __global__ void __launch_bounds__(kBlock, Occ<D>::kWavesPerEU) solve_kernel(Solv
         // appends to the other one)
         if (Words<WM>::kLds) {
             using T = typename Words<WM>::T;
-            T* lw = reinterpret_cast<T*>(lds_w);
-            const T* gw = static_cast<const T*>(p.rword);
-            for (int q = tid; q < na; q += kBlock) {
-                const int i = st.aff_list[q];
-                lw[i] = gw[i];
+            if (static_cast<int64_t>(na) * 64 > static_cast<int64_t>(p.m) * static_cast<int64_t>(sizeof(T))) {
+                // many rows: a 64-byte line per scattered word costs more
+                // than copying every word again
+                stage_words<WM>(p, lds_w);
+            } else {
+                T* lw = reinterpret_cast<T*>(lds_w);
+                const T* gw = static_cast<const T*>(p.rword);
+                for (int q = tid; q < na; q += kBlock) {
+                    const int i = st.aff_list[q];
+                    lw[i] = gw[i];
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
         ++l;
         if (gtid == 0) {
