@@ -990,7 +990,9 @@ __device__ __noinline__ void solve_instance(const l0_problem& P_in, const BatchP
         const int long_cap = (nthr >> 6) * 64;
         const lptr<int> long_rows = L.queue + kBatchQueue;
         int delta = 0;
-        for (int64_t q = gt; q < na; q += gstep) {
+        // rows dealt round-robin over the team's members (entry q to member
+        // q mod tsize), so that a short list is spread over the team
+        for (int64_t q = static_cast<int64_t>(tid) * tsize + rank; q < na; q += gstep) {
             const int i = s.aff_list[q];
             const int cnt = s.slot_cnt[i];
             if (cnt <= kShortList) {
